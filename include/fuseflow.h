@@ -1,0 +1,256 @@
+/*
+ * fuseflow.h — C ABI of the MI355X (gfx950) fusion library for FUSE-Flow
+ * (frame-wise confidence- and consistency-weighted multi-view point fusion with an
+ * adaptive spatial hash).
+ *
+ * What one call computes (paper Sec. II):
+ *   Sec. II.1, Eq. 1   input: N cameras with intrinsics K_i, extrinsics T_i, depth D_i,
+ *                      per-pixel confidence C_i (Sec. II.2, Eq. 2) and optional RGB I_i;
+ *                      output: one fused point cloud per time step, frame-wise and stateless.
+ *   Sec. II.4, Eq. 8-9 pixel-wise back-projection and confidence gating (C > tau).
+ *   Sec. II.5(1) a-e   world transform, extents, coarse density grid, density-adaptive
+ *                      refinement, assignment of every point to its cell (spatial hash).
+ *   Sec. II.5(2) a-c   per cell the three most confident points; for each, distance
+ *                      consistency V (Eq. 4-7) against at most K locally relevant views;
+ *                      joint weight w = C V (Eq. 10).
+ *   Sec. II.5(3)       weighted fusion of each cell's representatives (Eq. 11).
+ *
+ * Readings of points the paper leaves open (all fixed here, bit-for-bit):
+ *   - world_to_cam is [R | t] (world -> camera); Eq. 8 applies its inverse.
+ *   - depth is z-depth; pixel (x, y) has its centre at integer coordinates.
+ *   - a pixel is kept when depth is finite and > 0, C > tau (strict) and the
+ *     back-projected point is finite; otherwise it is dropped (Eq. 9's "0").
+ *   - coarse grid: coarse_res cells along the longest extent, edge rounded up to a power of
+ *     two; level L = smallest L <= max_level with count <= target_per_cell * 4^L.
+ *   - representatives: C descending, then x, y, z ascending, then pixel id.
+ *   - local views: other cameras whose image contains the nearest-pixel projection (point
+ *     in front), ranked by squared distance to the camera centre (ties: centre x, y, z,
+ *     camera index); the first min(K, N) - 1 are used; a view with no finite positive depth
+ *     at that pixel is skipped; V = exp(-sum d^2 / (m sigma^2)) over the m views used.
+ *   - fusion: xyz = sum(w p) / sum(w); weight = mean w; rgb = rint(sum(w rgb) / sum(w)).
+ *
+ * Conventions for every call:
+ *   - All image pointers in ff_view and all pointers in ff_output are DEVICE pointers on the
+ *     context's device.  Images are row-major with pitch = width (no padding).
+ *   - ff_camera, ff_view, ff_frame, ff_params and ff_output structs themselves are HOST
+ *     memory, read during the call only (they may be reused as soon as the call returns).
+ *   - Calls are asynchronous and ordered on the given stream (a hipStream_t passed as
+ *     void*, NULL = the null stream).  The caller owns inputs and outputs and must keep them
+ *     alive until the work queued on the stream completes.
+ *   - Return values report errors the host can detect (bad arguments, allocation failure,
+ *     HIP errors).  Data-dependent outcomes are written to device memory: *count receives
+ *     the number of fused points S; if S > capacity only the first `capacity` points are
+ *     written and *status becomes FF_DEV_OVERFLOW.  capacity >= sum(W*H) never overflows.
+ *   - Pixel ids are frame-global: camera-major (cameras in the order given), then y*W + x.
+ *     A frame must have fewer than 2^32 pixels.
+ *   - A context is not thread-safe: calls on one context must not overlap from several
+ *     host threads; work of successive calls on different streams is ordered by the
+ *     library (it reuses one workspace).
+ */
+#ifndef FUSEFLOW_H
+#define FUSEFLOW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ff_status {
+    FF_OK = 0,
+    FF_ERR_INVALID_ARG = 1,   /* a pointer, size or parameter is out of range */
+    FF_ERR_OOM = 2,           /* device or pinned allocation failed, or over the budget */
+    FF_ERR_BUSY = 3,          /* server: no free slot right now (non-blocking submit) */
+    FF_ERR_HIP = 4,           /* a HIP runtime call failed */
+    FF_ERR_NOT_FOUND = 5      /* server: unknown ticket */
+} ff_status;
+
+/* ff_params.flags: the paper's ablations (Sec. III, Table II) */
+enum {
+    FF_NO_MF = 1u,   /* no measurement confidence: C := 1, gate on depth only */
+    FF_NO_DC = 2u,   /* no distance consistency: V := 1 */
+    FF_NO_SA = 4u    /* no spatial-hash aggregation: every gated point is its own output,
+                        in pixel-id order, with V computed per point; keys = pixel ids */
+};
+
+/* values of *ff_output.status */
+enum { FF_DEV_OK = 0, FF_DEV_OVERFLOW = 1 };
+
+typedef struct ff_camera {
+    int32_t width, height;        /* pixels */
+    float fx, fy, cx, cy;         /* intrinsics K (pixel units) */
+    float world_to_cam[12];       /* [R | t] row-major 3x4: X_cam = R X_world + t */
+} ff_camera;
+
+typedef struct ff_view {
+    const float* depth;           /* device, height*width FP32 z-depth (m); <= 0 or NaN = none */
+    const float* conf;            /* device, height*width FP32 confidence in [0, 1] */
+    const uint8_t* rgb;           /* device, height*width*3 uint8, or NULL */
+} ff_view;
+
+typedef struct ff_params {
+    float tau;                    /* Eq. 9 gate threshold (paper: 0.6) */
+    int32_t k_views;              /* K of Eq. 7, own camera included, 1..8 (default 4) */
+    float sigma;                  /* Eq. 7 tolerance in metres (default 0.02) */
+    int32_t coarse_res;           /* coarse cells on the longest axis, power of two <= 128 (64) */
+    int32_t max_level;            /* deepest refinement level (6) */
+    int32_t target_per_cell;      /* refinement target occupancy (16) */
+    int32_t level_override;       /* -1, or a level used in every coarse cell */
+    uint32_t flags;               /* FF_NO_MF | FF_NO_DC | FF_NO_SA */
+} ff_params;
+
+typedef struct ff_output {
+    float* xyz;                   /* device [capacity][3] fused points (world, m) */
+    float* weight;                /* device [capacity] mean joint weight of the cell */
+    uint8_t* rgb;                 /* device [capacity][3] or NULL (needs rgb on every view) */
+    uint32_t* n_members;          /* device [capacity] gated points in the cell, or NULL */
+    uint32_t* reps;               /* device [capacity][3] representative pixel ids,
+                                     0xFFFFFFFF padded, or NULL */
+    uint64_t* keys;               /* device [capacity] cell key, or NULL:
+                                     (coarse << 3Lmax) | (lz << 2Lmax) | (ly << Lmax) | lx */
+    uint32_t* member_offsets;     /* device [capacity + 1] or NULL: cell s owns
+                                     member_ids[member_offsets[s] .. member_offsets[s+1]) */
+    uint32_t* member_ids;         /* device [member_capacity] or NULL: pixel ids of every
+                                     gated point grouped by cell, pixel-id order inside */
+    uint32_t capacity;            /* entries available in the per-point arrays */
+    uint32_t member_capacity;     /* entries available in member_ids */
+    uint32_t* count;              /* device [1]: S, the number of fused points */
+    int32_t* status;              /* device [1]: FF_DEV_OK or FF_DEV_OVERFLOW */
+    uint32_t* info;               /* device [4] or NULL: M (gated points), S, R
+                                     (representatives), sort key bits */
+} ff_output;
+
+typedef struct ff_frame {
+    int32_t n_cams;
+    const ff_camera* cams;        /* host [n_cams] */
+    const ff_view* views;         /* host [n_cams] */
+} ff_frame;
+
+typedef struct ff_context ff_context;
+
+/* Launch/tuning knobs of the device path (chosen by ff_autotune or set by hand). */
+typedef struct ff_tuning {
+    int32_t radix_bits;           /* digit width of the LSD radix sort: 4, 6 or 8 */
+    int32_t sort_items;           /* keys per thread per sort tile: 4, 8 or 16 */
+    int32_t cells_block;          /* threads per block in the per-cell phase: 64..1024 */
+    int32_t use_graph;            /* 1: ff_fuse_batch replays a cached HIP graph (default) */
+} ff_tuning;
+
+/* Library version string. */
+const char* ff_version(void);
+const char* ff_status_string(ff_status s);
+
+/* Paper constants and this library's defaults (tau 0.6, K 4, sigma 0.02, 64, 6, 16, -1, 0). */
+void ff_params_default(ff_params* p);
+
+/* Create a context on `device` able to take batches of up to max_frames frames holding
+ * max_pixels pixels and max_cameras cameras in total.  All device workspace is allocated
+ * here (nothing is allocated per call afterwards).  FF_ERR_OOM if it does not fit. */
+ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
+                            int32_t max_cameras, int32_t max_frames);
+void ff_context_destroy(ff_context* ctx);
+
+/* Device workspace bytes a context with these limits allocates. */
+uint64_t ff_workspace_bytes(uint64_t max_pixels, int32_t max_cameras, int32_t max_frames);
+
+/* Fuse one frame (Sec. II) with one kernel per step. */
+ff_status ff_fuse(ff_context* ctx, int32_t n_cams, const ff_camera* cams,
+                  const ff_view* views, const ff_params* params, const ff_output* out,
+                  void* stream);
+
+/* Fuse n_frames independent frames together: every step runs once over all cameras of all
+ * frames (uneven resolutions welcome; the frames are kept apart by disjoint key ranges), and
+ * the launches are replayed from a HIP graph cached per batch shape (resolution mix, grid
+ * parameters, tuning).  outs[f] receives exactly what ff_fuse would produce for frame f. */
+ff_status ff_fuse_batch(ff_context* ctx, int32_t n_frames, const ff_frame* frames,
+                        const ff_params* params, const ff_output* outs, void* stream);
+
+/* Tuning: get/set the knobs; autotune times candidate settings on the given batch shape
+ * (synchronises the stream) and keeps the fastest, cached by the resolution mix. */
+ff_status ff_get_tuning(const ff_context* ctx, ff_tuning* t);
+ff_status ff_set_tuning(ff_context* ctx, const ff_tuning* t);
+ff_status ff_autotune(ff_context* ctx, int32_t n_frames, const ff_frame* frames,
+                      const ff_params* params, const ff_output* outs, void* stream,
+                      ff_tuning* chosen);
+
+/* Per-kernel timing.  While enabled, ff_fuse brackets every kernel it launches with HIP
+ * events on the call's stream (ff_fuse_batch then launches directly instead of replaying a
+ * graph).  Slots: 0 prep, 1 back-project+AABB, 2 coarse histogram, 3..5 coarse scan,
+ * 6 keys, 7 cell heads, 8 cells (top-3, consistency, fusion), 9 final, 16+k radix pass k. */
+#define FF_TRACE_SLOTS 32
+typedef struct ff_trace {
+    double total_ms[FF_TRACE_SLOTS];   /* summed kernel time per slot */
+    uint64_t launches[FF_TRACE_SLOTS]; /* launches timed per slot */
+    uint64_t calls;                    /* ff_fuse / ff_fuse_batch calls timed */
+} ff_trace;
+ff_status ff_trace_enable(ff_context* ctx, int32_t on);   /* on resets the totals */
+ff_status ff_trace_read(ff_context* ctx, ff_trace* out);  /* waits for the timed work */
+const char* ff_trace_slot_name(int32_t slot);
+
+/* ------------------------------------------------------------------------------ serving
+ * A streaming loop over several rigs (the paper's per-frame statelessness, Sec. II.1, is
+ * what makes frames of different rigs independent work).  Frames are admitted as they
+ * arrive into batches sized by the device memory budget, run on `lanes` concurrent
+ * workspaces/streams (buffers and tables stay resident), and their latency (completion minus
+ * arrival) is recorded.  A frame's result is bit-identical to ff_fuse on the same frame.
+ * All HIP work of a server happens on its own scheduler thread. */
+
+typedef struct ff_server ff_server;
+
+typedef struct ff_server_config {
+    uint64_t hbm_budget_bytes;    /* device memory for all lane workspaces together */
+    int32_t lanes;                /* concurrent batches (one stream + workspace each), 1..8 */
+    int32_t max_batch_frames;     /* frames per batch, 1..64 */
+    int32_t max_cameras;          /* cameras per batch, 1..1024 */
+    int32_t max_pending;          /* submitted but not started frames; beyond: FF_ERR_BUSY */
+    int32_t plain;                /* 1: baseline loop, one frame at a time through ff_fuse,
+                                     the next frame starts after the previous completed */
+} ff_server_config;
+
+typedef struct ff_stats {
+    uint64_t frames;              /* completed frames */
+    uint64_t pixels;              /* their input pixels */
+    uint64_t batches;             /* launches (batches) */
+    double first_arrival_s;       /* server clock of the first completed frame's arrival */
+    double last_done_s;           /* server clock of the last completion */
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* frame latency: completion - arrival */
+    double px_per_s;              /* pixels / (last_done - first_arrival) */
+    double mean_batch_frames;
+} ff_stats;
+
+/* Defaults: 2 lanes, 16 frames per batch, 256 cameras, 4096 pending, not plain. */
+void ff_server_config_default(ff_server_config* cfg);
+
+/* Creates the lanes.  Each lane's workspace takes at most budget / lanes bytes; frames larger
+ * than a lane can hold are refused at submit with FF_ERR_OOM.  FF_ERR_OOM here if not even
+ * one 4096-pixel frame fits. */
+ff_status ff_server_create(ff_server** out, int device, const ff_server_config* cfg);
+void ff_server_destroy(ff_server* s);
+
+/* Largest frame (pixels) one lane admits. */
+uint64_t ff_server_lane_pixels(const ff_server* s);
+
+/* Seconds on the server clock (steady clock, zero at creation). */
+double ff_server_now(const ff_server* s);
+
+/* Queue one frame of rig `rig_id` arriving at `arrival_s` on the server clock (a time in the
+ * past means now).  The host structs are copied; the device images and `out` buffers must
+ * stay valid until the frame is done.  FF_ERR_BUSY when max_pending frames wait already. */
+ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
+                           const ff_params* params, const ff_output* out, double arrival_s,
+                           uint64_t* ticket);
+
+/* done = 1 once the frame's results are in its output buffers. */
+ff_status ff_server_poll(ff_server* s, uint64_t ticket, int32_t* done);
+ff_status ff_server_wait(ff_server* s, uint64_t ticket);
+/* Wait until every submitted frame is done. */
+ff_status ff_server_drain(ff_server* s);
+
+ff_status ff_server_stats(const ff_server* s, ff_stats* st);
+/* Forget completed frames' latencies (stats restart from zero). */
+ff_status ff_server_reset_stats(ff_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FUSEFLOW_H */

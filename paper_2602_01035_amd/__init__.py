@@ -1,0 +1,482 @@
+"""Python binding of the MI355X fusion library (libfuseflow.so, C ABI in include/fuseflow.h).
+
+Argument marshalling only: every step of the fusion path runs in the HIP kernels of the
+library.  PyTorch provides device memory and streams.  If the shared library is missing
+this module raises at import time — there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfuseflow.so")
+
+FF_OK, FF_ERR_INVALID_ARG, FF_ERR_OOM, FF_ERR_BUSY, FF_ERR_HIP, FF_ERR_NOT_FOUND = range(6)
+FF_NO_MF, FF_NO_DC, FF_NO_SA = 1, 2, 4
+FF_DEV_OK, FF_DEV_OVERFLOW = 0, 1
+PAD = 0xFFFFFFFF
+
+
+class FuseFlowError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib.ff_status_string(status).decode()} ({status})")
+
+
+# ----------------------------------------------------------------------------- C structs
+
+class ff_camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("world_to_cam", ctypes.c_float * 12)]
+
+
+class ff_view(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("conf", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
+
+
+class ff_params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_float), ("k_views", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("coarse_res", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("target_per_cell", ctypes.c_int32),
+                ("level_override", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class ff_output(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("n_members", ctypes.c_void_p), ("reps", ctypes.c_void_p),
+                ("keys", ctypes.c_void_p), ("member_offsets", ctypes.c_void_p),
+                ("member_ids", ctypes.c_void_p), ("capacity", ctypes.c_uint32),
+                ("member_capacity", ctypes.c_uint32), ("count", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
+class ff_frame(ctypes.Structure):
+    _fields_ = [("n_cams", ctypes.c_int32), ("cams", ctypes.POINTER(ff_camera)),
+                ("views", ctypes.POINTER(ff_view))]
+
+
+class ff_tuning(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_int32), ("sort_items", ctypes.c_int32),
+                ("cells_block", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class ff_trace(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double * 32), ("launches", ctypes.c_uint64 * 32),
+                ("calls", ctypes.c_uint64)]
+
+
+class ff_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("lanes", ctypes.c_int32),
+                ("max_batch_frames", ctypes.c_int32), ("max_cameras", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("plain", ctypes.c_int32)]
+
+
+class ff_stats(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_uint64), ("pixels", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("first_arrival_s", ctypes.c_double),
+                ("last_done_s", ctypes.c_double), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("px_per_s", ctypes.c_double),
+                ("mean_batch_frames", ctypes.c_double)]
+
+
+# ----------------------------------------------------------------------------- library
+
+EXPORTS = {
+    "ff_version": (ctypes.c_char_p, []),
+    "ff_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ff_params_default": (None, [ctypes.POINTER(ff_params)]),
+    "ff_context_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                         ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]),
+    "ff_context_destroy": (None, [ctypes.c_void_p]),
+    "ff_workspace_bytes": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32]),
+    "ff_fuse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_camera),
+                               ctypes.POINTER(ff_view), ctypes.POINTER(ff_params),
+                               ctypes.POINTER(ff_output), ctypes.c_void_p]),
+    "ff_fuse_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
+                                     ctypes.POINTER(ff_params), ctypes.POINTER(ff_output),
+                                     ctypes.c_void_p]),
+    "ff_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_tuning)]),
+    "ff_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_tuning)]),
+    "ff_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
+                                   ctypes.POINTER(ff_params), ctypes.POINTER(ff_output),
+                                   ctypes.c_void_p, ctypes.POINTER(ff_tuning)]),
+    "ff_trace_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ff_trace_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_trace)]),
+    "ff_trace_slot_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ff_server_config_default": (None, [ctypes.POINTER(ff_server_config)]),
+    "ff_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.POINTER(ff_server_config)]),
+    "ff_server_destroy": (None, [ctypes.c_void_p]),
+    "ff_server_lane_pixels": (ctypes.c_uint64, [ctypes.c_void_p]),
+    "ff_server_now": (ctypes.c_double, [ctypes.c_void_p]),
+    "ff_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
+                                        ctypes.POINTER(ff_params), ctypes.POINTER(ff_output),
+                                        ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
+    "ff_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "ff_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ff_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
+    "ff_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_stats)]),
+    "ff_server_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2602_01035_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def version() -> str:
+    return _lib.ff_version().decode()
+
+
+# ----------------------------------------------------------------------------- helpers
+
+class Params:
+    """ff_params with the library defaults; keyword overrides."""
+
+    def __init__(self, **kw):
+        p = ff_params()
+        _lib.ff_params_default(ctypes.byref(p))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown parameter {k!r}")
+            setattr(p, k, v)
+        self.c = p
+
+    def __getattr__(self, k):
+        return getattr(self.__dict__["c"], k)
+
+
+def _check(status: int, where: str):
+    if status != FF_OK:
+        raise FuseFlowError(status, where)
+
+
+def _camera(cam) -> ff_camera:
+    c = ff_camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    T = [float(v) for row in cam.world_to_cam for v in row]
+    if len(T) != 12:
+        raise ValueError("world_to_cam must be 3x4")
+    for i, v in enumerate(T):
+        c.world_to_cam[i] = v
+    return c
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_image(t, H, W, dtype, name, channels=None):
+    torch = _torch()
+    shape = (H, W) if channels is None else (H, W, channels)
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a ROCm device tensor")
+    if t.dtype != dtype or tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {shape}")
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Output:
+    """Device output buffers of one frame (torch tensors) and the ff_output view of them."""
+
+    def __init__(self, capacity: int, member_capacity: int = 0, rgb: bool = False,
+                 members: bool = False, device=None):
+        torch = _torch()
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        cap = max(1, int(capacity))
+        self.capacity = cap
+        self.xyz = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+        self.weight = torch.empty(cap, dtype=torch.float32, device=dev)
+        self.rgb = torch.empty((cap, 3), dtype=torch.uint8, device=dev) if rgb else None
+        self.n_members = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.reps = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        self.keys = torch.empty(cap, dtype=torch.int64, device=dev)
+        self.member_offsets = torch.empty(cap + 1, dtype=torch.int32, device=dev) if members else None
+        mcap = max(1, int(member_capacity)) if members else 0
+        self.member_capacity = mcap
+        self.member_ids = torch.empty(mcap, dtype=torch.int32, device=dev) if members else None
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.info = torch.zeros(4, dtype=torch.int32, device=dev)
+
+    def c(self) -> ff_output:
+        o = ff_output()
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        o.xyz, o.weight, o.rgb = ptr(self.xyz), ptr(self.weight), ptr(self.rgb)
+        o.n_members, o.reps, o.keys = ptr(self.n_members), ptr(self.reps), ptr(self.keys)
+        o.member_offsets, o.member_ids = ptr(self.member_offsets), ptr(self.member_ids)
+        o.capacity, o.member_capacity = self.capacity, self.member_capacity
+        o.count, o.status, o.info = ptr(self.count), ptr(self.status), ptr(self.info)
+        return o
+
+    def result(self) -> Dict:
+        """Synchronise and return the fused cloud as NumPy arrays (cells in key order)."""
+        import numpy as np
+        _torch().cuda.synchronize()
+        S = int(self.count.item())
+        st = int(self.status.item())
+        n = min(S, self.capacity)
+        u32 = lambda t: t.cpu().numpy().view(np.uint32)
+        out = dict(count=S, status=st, xyz=self.xyz[:n].cpu().numpy(),
+                   weight=self.weight[:n].cpu().numpy(),
+                   rgb=self.rgb[:n].cpu().numpy() if self.rgb is not None else None,
+                   n_members=u32(self.n_members[:n]), reps=u32(self.reps[:n]),
+                   keys=self.keys[:n].cpu().numpy().view(np.uint64),
+                   info=u32(self.info))
+        if self.member_offsets is not None:
+            M = int(out["info"][0])
+            out["member_offsets"] = u32(self.member_offsets[:n + 1])
+            out["member_ids"] = u32(self.member_ids[:min(M, self.member_capacity)])
+        return out
+
+
+class Context:
+    """A device workspace for batches of up to max_frames frames / max_pixels pixels."""
+
+    def __init__(self, max_pixels: int, max_cameras: int = 64, max_frames: int = 1,
+                 device: Optional[int] = None):
+        torch = _torch()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.ff_context_create(ctypes.byref(h), device, int(max_pixels),
+                                      int(max_cameras), int(max_frames)), "ff_context_create")
+        self.h = h
+        self.max_pixels, self.max_cameras, self.max_frames = max_pixels, max_cameras, max_frames
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ff_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tuning
+    def tuning(self) -> Dict:
+        t = ff_tuning()
+        _check(_lib.ff_get_tuning(self.h, ctypes.byref(t)), "ff_get_tuning")
+        return {k: getattr(t, k) for k, _ in ff_tuning._fields_}
+
+    def set_tuning(self, **kw):
+        t = ff_tuning()
+        _check(_lib.ff_get_tuning(self.h, ctypes.byref(t)), "ff_get_tuning")
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(_lib.ff_set_tuning(self.h, ctypes.byref(t)), "ff_set_tuning")
+
+    # -- kernel timing
+    def trace(self, on: bool = True):
+        _check(_lib.ff_trace_enable(self.h, int(on)), "ff_trace_enable")
+
+    def trace_read(self) -> Dict:
+        t = ff_trace()
+        _check(_lib.ff_trace_read(self.h, ctypes.byref(t)), "ff_trace_read")
+        out = {}
+        for s in range(32):
+            if t.launches[s]:
+                out[_lib.ff_trace_slot_name(s).decode()] = dict(
+                    total_ms=t.total_ms[s], launches=int(t.launches[s]),
+                    mean_ms=t.total_ms[s] / t.launches[s])
+        return dict(calls=int(t.calls), kernels=out)
+
+    # -- marshalling
+    @staticmethod
+    def _views(cams, depth, conf, rgb):
+        torch = _torch()
+        n = len(cams)
+        if len(depth) != n or len(conf) != n or (rgb is not None and len(rgb) != n):
+            raise ValueError("one depth, confidence (and rgb) image per camera")
+        ccams = (ff_camera * n)()
+        views = (ff_view * n)()
+        for k, cam in enumerate(cams):
+            ccams[k] = _camera(cam)
+            H, W = int(cam.height), int(cam.width)
+            _check_image(depth[k], H, W, torch.float32, f"depth[{k}]")
+            _check_image(conf[k], H, W, torch.float32, f"conf[{k}]")
+            views[k].depth = depth[k].data_ptr()
+            views[k].conf = conf[k].data_ptr()
+            if rgb is not None:
+                _check_image(rgb[k], H, W, torch.uint8, f"rgb[{k}]", channels=3)
+                views[k].rgb = rgb[k].data_ptr()
+        return ccams, views
+
+    def fuse(self, cams, depth: Sequence, conf: Sequence, rgb: Optional[Sequence] = None,
+             params: Optional[Params] = None, out: Optional[Output] = None, stream=None,
+             members: bool = False) -> Output:
+        """One frame through the per-step kernels (ff_fuse). Asynchronous on `stream`."""
+        ccams, views = self._views(cams, depth, conf, rgb)
+        P = sum(int(c.width) * int(c.height) for c in cams)
+        if out is None:
+            out = Output(P, P, rgb=rgb is not None, members=members)
+        prm = (params or Params()).c
+        o = out.c()
+        _check(_lib.ff_fuse(self.h, len(cams), ccams, views, ctypes.byref(prm), ctypes.byref(o),
+                            _stream_ptr(stream)), "ff_fuse")
+        return out
+
+    def _frames(self, frames):
+        keep, cf = [], (ff_frame * len(frames))()
+        for f, fr in enumerate(frames):
+            ccams, views = self._views(fr["cams"], fr["depth"], fr["conf"], fr.get("rgb"))
+            keep.append((ccams, views))
+            cf[f].n_cams = len(fr["cams"])
+            cf[f].cams = ctypes.cast(ccams, ctypes.POINTER(ff_camera))
+            cf[f].views = ctypes.cast(views, ctypes.POINTER(ff_view))
+        return cf, keep
+
+    def fuse_batch(self, frames: List[Dict], params: Optional[Params] = None,
+                   outs: Optional[List[Output]] = None, stream=None,
+                   members: bool = False) -> List[Output]:
+        """Several frames in one persistent launch (ff_fuse_batch).  Each frame is a dict with
+        cams, depth, conf and optional rgb."""
+        cf, keep = self._frames(frames)
+        if outs is None:
+            outs = []
+            for fr in frames:
+                P = sum(int(c.width) * int(c.height) for c in fr["cams"])
+                outs.append(Output(P, P, rgb=fr.get("rgb") is not None, members=members))
+        co = (ff_output * len(frames))(*[o.c() for o in outs])
+        prm = (params or Params()).c
+        _check(_lib.ff_fuse_batch(self.h, len(frames), cf, ctypes.byref(prm), co,
+                                  _stream_ptr(stream)), "ff_fuse_batch")
+        return outs
+
+    def autotune(self, frames: List[Dict], params: Optional[Params] = None,
+                 outs: Optional[List[Output]] = None, stream=None) -> Dict:
+        cf, keep = self._frames(frames)
+        if outs is None:
+            outs = [Output(sum(int(c.width) * int(c.height) for c in fr["cams"]),
+                           rgb=fr.get("rgb") is not None) for fr in frames]
+        co = (ff_output * len(frames))(*[o.c() for o in outs])
+        prm = (params or Params()).c
+        t = ff_tuning()
+        _check(_lib.ff_autotune(self.h, len(frames), cf, ctypes.byref(prm), co,
+                                _stream_ptr(stream), ctypes.byref(t)), "ff_autotune")
+        return {k: getattr(t, k) for k, _ in ff_tuning._fields_}
+
+
+class Server:
+    """Continuous-batching server (C++ scheduler thread inside the library).
+
+    submit() queues a frame (device tensors) arriving at `arrival_s` on the server clock;
+    results land in the returned Output.  plain=True gives the one-frame-at-a-time baseline."""
+
+    def __init__(self, hbm_budget_bytes: int = 16 << 30, lanes: int = 2,
+                 max_batch_frames: int = 16, max_cameras: int = 256, max_pending: int = 4096,
+                 plain: bool = False, device: Optional[int] = None):
+        torch = _torch()
+        if device is None:
+            device = torch.cuda.current_device()
+        cfg = ff_server_config()
+        _lib.ff_server_config_default(ctypes.byref(cfg))
+        cfg.hbm_budget_bytes, cfg.lanes = int(hbm_budget_bytes), int(lanes)
+        cfg.max_batch_frames, cfg.max_cameras = int(max_batch_frames), int(max_cameras)
+        cfg.max_pending, cfg.plain = int(max_pending), int(bool(plain))
+        h = ctypes.c_void_p()
+        _check(_lib.ff_server_create(ctypes.byref(h), device, ctypes.byref(cfg)), "ff_server_create")
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.ff_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def lane_pixels(self) -> int:
+        return int(_lib.ff_server_lane_pixels(self.h))
+
+    def now(self) -> float:
+        return float(_lib.ff_server_now(self.h))
+
+    def submit(self, rig: int, frame: Dict, out: "Output", params: Optional[Params] = None,
+               arrival_s: float = 0.0) -> int:
+        ccams, views = Context._views(frame["cams"], frame["depth"], frame["conf"],
+                                      frame.get("rgb"))
+        fr = ff_frame(len(frame["cams"]), ctypes.cast(ccams, ctypes.POINTER(ff_camera)),
+                      ctypes.cast(views, ctypes.POINTER(ff_view)))
+        o = out.c()
+        prm = (params or Params()).c
+        t = ctypes.c_uint64()
+        _check(_lib.ff_server_submit(self.h, int(rig), ctypes.byref(fr), ctypes.byref(prm),
+                                     ctypes.byref(o), float(arrival_s), ctypes.byref(t)),
+               "ff_server_submit")
+        self._keep[t.value] = (frame, out)       # device buffers stay alive until done
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(_lib.ff_server_poll(self.h, ticket, ctypes.byref(d)), "ff_server_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(_lib.ff_server_wait(self.h, ticket), "ff_server_wait")
+        self._keep.pop(ticket, None)
+
+    def drain(self):
+        _check(_lib.ff_server_drain(self.h), "ff_server_drain")
+        self._keep.clear()
+
+    def stats(self) -> Dict:
+        s = ff_stats()
+        _check(_lib.ff_server_stats(self.h, ctypes.byref(s)), "ff_server_stats")
+        return {k: getattr(s, k) for k, _ in ff_stats._fields_}
+
+    def reset_stats(self):
+        _check(_lib.ff_server_reset_stats(self.h), "ff_server_reset_stats")
+
+
+def to_device(frame, device="cuda", with_rgb=True) -> Dict:
+    """Upload a synthetic/host frame (cams, depth, conf, rgb as NumPy) to device tensors."""
+    torch = _torch()
+    up = lambda a: torch.from_numpy(a).to(device).contiguous()
+    d = dict(cams=list(frame.cams), depth=[up(x) for x in frame.depth],
+             conf=[up(x) for x in frame.conf])
+    if with_rgb and frame.rgb is not None:
+        d["rgb"] = [up(x) for x in frame.rgb]
+    return d
+
+
+__all__ = ["Context", "Output", "Params", "Server", "FuseFlowError", "to_device", "version", "lib",
+           "FF_NO_MF", "FF_NO_DC", "FF_NO_SA", "PAD", "EXPORTS"]

@@ -1,0 +1,376 @@
+// Continuous-batching server for streams of frames from several rigs.
+//
+// Frames are stateless and independent (one fused cloud per time step, nothing carried
+// across frames), so frames of different rigs can share a launch.  The server keeps
+// `lanes` resident workspaces, each with its own stream.  A scheduler thread admits arrived
+// frames into the next free lane as one batch (FIFO by arrival, as many as fit the lane's
+// pixel budget and frame limit, equal parameters), launches it with ff_fuse_batch and
+// polls its completion event; the next batch can start on another lane while the previous
+// one still runs.  Latency = completion (observed by the scheduler thread) - arrival.
+//
+// The plain baseline (config.plain = 1) runs the same trace one frame at a time through
+// ff_fuse and starts a frame only after the previous one completed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fuseflow.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Job {
+    uint64_t ticket;
+    int32_t rig;
+    double arrival;
+    uint64_t pixels;
+    std::vector<ff_camera> cams;
+    std::vector<ff_view> views;
+    ff_params params;
+    ff_output out;
+};
+
+struct Lane {
+    ff_context* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Job> batch;
+};
+
+bool same_params(const ff_params& a, const ff_params& b) {
+    return std::memcmp(&a, &b, sizeof(ff_params)) == 0;
+}
+
+}  // namespace
+
+struct ff_server {
+    int device = 0;
+    ff_server_config cfg{};
+    uint64_t lane_px = 0;
+    Clock::time_point t0;
+    std::vector<Lane> lanes;
+    // shared state (mutex)
+    std::mutex mu;
+    std::condition_variable cv_done;   // frames completed
+    std::condition_variable cv_work;   // new submissions
+    std::multimap<double, Job> pending;   // by arrival time (ties keep submission order)
+    std::unordered_map<uint64_t, int> state;   // ticket -> 0 queued, 1 running, 2 done
+    uint64_t next_ticket = 1;
+    uint64_t outstanding = 0;
+    bool stop = false;
+    ff_status error = FF_OK;
+    // stats (mutex)
+    std::vector<double> lat_ms;
+    uint64_t frames = 0, pixels = 0, batches = 0, batch_frames = 0;
+    double first_arrival = -1.0, last_done = 0.0;
+    std::thread worker;
+
+    double now() const {
+        return std::chrono::duration<double>(Clock::now() - t0).count();
+    }
+    void run();
+    bool launch(Lane& L, double t);
+    void complete(Lane& L, double t);
+};
+
+bool ff_server::launch(Lane& L, double t) {
+    // caller holds mu; take arrived frames FIFO while they fit this lane
+    L.batch.clear();
+    uint64_t px = 0, cams = 0;
+    const int max_frames = cfg.plain ? 1 : cfg.max_batch_frames;
+    for (auto it = pending.begin(); it != pending.end() && it->first <= t;) {
+        Job& j = it->second;
+        if ((int)L.batch.size() >= max_frames) break;
+        if (!L.batch.empty() && !same_params(j.params, L.batch.front().params)) break;
+        if (px + j.pixels > lane_px || cams + j.cams.size() > (uint64_t)cfg.max_cameras) break;
+        px += j.pixels;
+        cams += j.cams.size();
+        state[j.ticket] = 1;
+        L.batch.push_back(std::move(j));
+        it = pending.erase(it);
+    }
+    if (L.batch.empty()) return false;
+    std::vector<ff_frame> frames(L.batch.size());
+    std::vector<ff_output> outs(L.batch.size());
+    for (size_t i = 0; i < L.batch.size(); ++i) {
+        frames[i].n_cams = (int32_t)L.batch[i].cams.size();
+        frames[i].cams = L.batch[i].cams.data();
+        frames[i].views = L.batch[i].views.data();
+        outs[i] = L.batch[i].out;
+    }
+    ff_status st;
+    if (cfg.plain)
+        st = ff_fuse(L.ctx, frames[0].n_cams, frames[0].cams, frames[0].views,
+                     &L.batch[0].params, &outs[0], L.stream);
+    else
+        st = ff_fuse_batch(L.ctx, (int32_t)frames.size(), frames.data(), &L.batch[0].params,
+                           outs.data(), L.stream);
+    if (st == FF_OK && hipEventRecord(L.done, L.stream) != hipSuccess) st = FF_ERR_HIP;
+    if (st != FF_OK) error = st;
+    L.busy = true;     // completion (or the error) is reported through complete()
+    ++batches;
+    batch_frames += L.batch.size();
+    return true;
+}
+
+void ff_server::complete(Lane& L, double t) {
+    for (Job& j : L.batch) {
+        state[j.ticket] = 2;
+        if (first_arrival < 0 || j.arrival < first_arrival) first_arrival = j.arrival;
+        lat_ms.push_back((t - j.arrival) * 1e3);
+        ++frames;
+        pixels += j.pixels;
+        --outstanding;
+    }
+    last_done = std::max(last_done, t);
+    L.batch.clear();
+    L.busy = false;
+}
+
+void ff_server::run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        bool progressed = false;
+        // 1. completions (event queries are cheap and non-blocking)
+        for (Lane& L : lanes) {
+            if (!L.busy) continue;
+            hipError_t q = error == FF_OK ? hipEventQuery(L.done) : hipSuccess;
+            if (q == hipSuccess) {
+                complete(L, now());
+                progressed = true;
+            } else if (q != hipErrorNotReady) {
+                error = FF_ERR_HIP;
+                complete(L, now());
+                progressed = true;
+            }
+        }
+        if (progressed) cv_done.notify_all();
+        // 2. admissions into free lanes
+        const double t = now();
+        for (Lane& L : lanes) {
+            if (L.busy) continue;
+            if (pending.empty() || pending.begin()->first > t) break;
+            if (launch(L, t)) progressed = true;
+        }
+        if (stop && pending.empty() && std::none_of(lanes.begin(), lanes.end(),
+                                                    [](const Lane& L) { return L.busy; }))
+            break;
+        if (progressed) continue;
+        const bool any_busy = std::any_of(lanes.begin(), lanes.end(),
+                                          [](const Lane& L) { return L.busy; });
+        if (any_busy) {
+            // a batch is running: poll its event at a few-microsecond granularity
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(5));
+            lk.lock();
+        } else if (!pending.empty()) {
+            const double wait = pending.begin()->first - now();
+            if (wait > 2e-4) {
+                cv_work.wait_for(lk, std::chrono::duration<double>(wait - 1e-4));
+            } else if (wait > 0) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(5));
+                lk.lock();
+            }
+        } else {
+            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        }
+    }
+}
+
+extern "C" {
+
+void ff_server_config_default(ff_server_config* c) {
+    if (!c) return;
+    c->hbm_budget_bytes = 16ull << 30;
+    c->lanes = 2;
+    c->max_batch_frames = 16;
+    c->max_cameras = 256;
+    c->max_pending = 4096;
+    c->plain = 0;
+}
+
+ff_status ff_server_create(ff_server** out, int device, const ff_server_config* cfg) {
+    if (!out || !cfg) return FF_ERR_INVALID_ARG;
+    *out = nullptr;
+    ff_server_config c = *cfg;
+    if (c.plain) { c.lanes = 1; c.max_batch_frames = 1; }
+    if (c.lanes < 1 || c.lanes > 8 || c.max_batch_frames < 1 || c.max_batch_frames > 64 ||
+        c.max_cameras < 1 || c.max_cameras > 1024 || c.max_pending < 1)
+        return FF_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return FF_ERR_INVALID_ARG;
+    // largest lane (pixels) whose workspace fits budget / lanes
+    const uint64_t per_lane = c.hbm_budget_bytes / (uint64_t)c.lanes;
+    uint64_t lo = 0, hi = 0xFFFFFFFEull;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (ff_workspace_bytes(mid, c.max_cameras, c.max_batch_frames) <= per_lane) lo = mid;
+        else hi = mid - 1;
+    }
+    if (lo < 4096) return FF_ERR_OOM;
+    ff_server* s = new ff_server();
+    s->device = device;
+    s->cfg = c;
+    s->lane_px = lo;
+    s->t0 = Clock::now();
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(device);
+    s->lanes.resize(c.lanes);
+    ff_status st = FF_OK;
+    for (Lane& L : s->lanes) {
+        if ((st = ff_context_create(&L.ctx, device, lo, c.max_cameras, c.max_batch_frames)) != FF_OK)
+            break;
+        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
+            st = FF_ERR_HIP;
+            break;
+        }
+    }
+    (void)hipSetDevice(prev);
+    if (st != FF_OK) {
+        ff_server_destroy(s);
+        return st;
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return FF_OK;
+}
+
+void ff_server_destroy(ff_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (Lane& L : s->lanes) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+        if (L.ctx) ff_context_destroy(L.ctx);
+    }
+    delete s;
+}
+
+uint64_t ff_server_lane_pixels(const ff_server* s) { return s ? s->lane_px : 0; }
+
+double ff_server_now(const ff_server* s) { return s ? s->now() : 0.0; }
+
+ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
+                           const ff_params* params, const ff_output* out, double arrival_s,
+                           uint64_t* ticket) {
+    if (!s || !frame || !params || !out || !ticket || frame->n_cams < 1 || !frame->cams ||
+        !frame->views)
+        return FF_ERR_INVALID_ARG;
+    Job j;
+    j.rig = rig_id;
+    j.cams.assign(frame->cams, frame->cams + frame->n_cams);
+    j.views.assign(frame->views, frame->views + frame->n_cams);
+    j.params = *params;
+    j.out = *out;
+    j.pixels = 0;
+    for (const ff_camera& c : j.cams) {
+        if (c.width < 1 || c.height < 1) return FF_ERR_INVALID_ARG;
+        j.pixels += (uint64_t)c.width * (uint64_t)c.height;
+    }
+    if (j.pixels > s->lane_px || j.cams.size() > (size_t)s->cfg.max_cameras) return FF_ERR_OOM;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->error != FF_OK) return s->error;
+        if (s->pending.size() >= (size_t)s->cfg.max_pending) return FF_ERR_BUSY;
+        j.ticket = s->next_ticket++;
+        j.arrival = std::max(arrival_s, 0.0);
+        *ticket = j.ticket;
+        s->state[j.ticket] = 0;
+        ++s->outstanding;
+        const double a = j.arrival;
+        s->pending.emplace(a, std::move(j));
+    }
+    s->cv_work.notify_all();
+    return FF_OK;
+}
+
+ff_status ff_server_poll(ff_server* s, uint64_t ticket, int32_t* done) {
+    if (!s || !done) return FF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->state.find(ticket);
+    if (it == s->state.end()) return FF_ERR_NOT_FOUND;
+    *done = it->second == 2 ? 1 : 0;
+    return s->error;
+}
+
+ff_status ff_server_wait(ff_server* s, uint64_t ticket) {
+    if (!s) return FF_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->state.find(ticket);
+    if (it == s->state.end()) return FF_ERR_NOT_FOUND;
+    s->cv_done.wait(lk, [&] { return s->state[ticket] == 2 || s->error != FF_OK; });
+    return s->error;
+}
+
+ff_status ff_server_drain(ff_server* s) {
+    if (!s) return FF_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->outstanding == 0 || s->error != FF_OK; });
+    return s->error;
+}
+
+ff_status ff_server_stats(const ff_server* cs, ff_stats* st) {
+    if (!cs || !st) return FF_ERR_INVALID_ARG;
+    ff_server* s = const_cast<ff_server*>(cs);
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(st, 0, sizeof(*st));
+    st->frames = s->frames;
+    st->pixels = s->pixels;
+    st->batches = s->batches;
+    st->first_arrival_s = s->first_arrival;
+    st->last_done_s = s->last_done;
+    st->mean_batch_frames = s->batches ? (double)s->batch_frames / (double)s->batches : 0.0;
+    if (!s->lat_ms.empty()) {
+        std::vector<double> v = s->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            const size_t i = (size_t)std::min<double>(v.size() - 1, std::ceil(q * v.size()) - 1);
+            return v[i];
+        };
+        st->p50_ms = pct(0.50);
+        st->p99_ms = pct(0.99);
+        st->max_ms = v.back();
+        double sum = 0;
+        for (double x : v) sum += x;
+        st->mean_ms = sum / v.size();
+        const double span = s->last_done - s->first_arrival;
+        st->px_per_s = span > 0 ? (double)s->pixels / span : 0.0;
+    }
+    return s->error;
+}
+
+ff_status ff_server_reset_stats(ff_server* s) {
+    if (!s) return FF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->lat_ms.clear();
+    s->frames = s->pixels = s->batches = s->batch_frames = 0;
+    s->first_arrival = -1.0;
+    s->last_done = 0.0;
+    return FF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+"""Shared helpers of the GPU tests: run the library, compare against the oracle."""
+import numpy as np
+
+from oracle import core as O
+
+# Parity bar.  Integer/index results are compared bit for bit.  Floating point: the oracle
+# accumulates in float64 and the library's float64 continuous part differs only in the
+# last bits of exp/log, so 1e-5 relative (floor 1 m for coordinates, 1e-6 for weights) is
+# far above the expected gap while far below any plausible arithmetic mistake.
+XYZ_RTOL = 1e-5
+W_RTOL = 1e-5
+
+
+def oracle_params(p):
+    """library Params -> oracle Params"""
+    return O.Params(tau=float(np.float32(p.tau)), k_views=p.k_views, sigma=float(np.float32(p.sigma)),
+                    coarse_res=p.coarse_res, max_level=p.max_level,
+                    target_per_cell=p.target_per_cell, level_override=p.level_override,
+                    flags=p.flags)
+
+
+def run_gpu(ctx, frame, params=None, members=True, with_rgb=True, batch=False, stream=None):
+    import paper_2602_01035_amd as ff
+    dev = ff.to_device(frame, with_rgb=with_rgb)
+    if batch:
+        out = ctx.fuse_batch([dev], params=params, members=members, stream=stream)[0]
+    else:
+        out = ctx.fuse(dev["cams"], dev["depth"], dev["conf"], dev.get("rgb"), params=params,
+                       members=members, stream=stream)
+    return out.result()
+
+
+def compare(g, o, check_members=True, label=""):
+    """Assert GPU result g == oracle result o to the parity bar."""
+    S = len(o["keys"])
+    assert g["status"] == 0, (label, "status", g["status"])
+    assert g["count"] == S, (label, "S", g["count"], S)
+    assert np.array_equal(g["keys"], o["keys"]), (label, "keys")
+    assert np.array_equal(g["n_members"], o["n_members"]), (label, "n_members")
+    assert np.array_equal(g["reps"], o["reps"]), (label, "reps")
+    if check_members and "member_ids" in g:
+        assert np.array_equal(g["member_offsets"], o["member_offsets"]), (label, "offsets")
+        assert np.array_equal(g["member_ids"], o["member_ids"]), (label, "member ids")
+    if S:
+        scale = np.maximum(np.abs(o["xyz"]).max(axis=1), 1.0)
+        err = np.abs(g["xyz"].astype(np.float64) - o["xyz"]).max(axis=1)
+        bad = np.flatnonzero(err > XYZ_RTOL * scale)
+        assert len(bad) == 0, (label, "xyz", bad[:5], err[bad[:5]])
+        werr = np.abs(g["weight"].astype(np.float64) - o["weight"])
+        wbad = np.flatnonzero(werr > W_RTOL * np.maximum(o["weight"], 1e-6))
+        assert len(wbad) == 0, (label, "weight", wbad[:5], g["weight"][wbad[:5]],
+                                o["weight"][wbad[:5]])
+        if o.get("rgb") is not None and g.get("rgb") is not None:
+            d = np.abs(g["rgb"].astype(int) - o["rgb"].astype(int))
+            assert d.max() <= 1, (label, "rgb")

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Bit-exact: point counts, cell keys, membership, representative ids.  Within 1e-5
+(relative): fused coordinates and weights.  Every case prints its name before the GPU step.
+"""
+import numpy as np
+import pytest
+
+from oracle import core as O
+from synth import make_config, make_frame, ring_cameras
+from synth.scenes import make_camera, _scene_c1, _scene_c2
+from tests.conftest import cached_frame
+from tests.gpu_helpers import compare, oracle_params, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ff():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2602_01035_amd as ff
+    return ff
+
+
+@pytest.fixture(scope="module")
+def ctx(ff):
+    c = ff.Context(max_pixels=16_000_000, max_cameras=64, max_frames=8)
+    yield c
+    c.close()
+
+
+def _case(ctx, ff, frame, label, params=None, with_rgb=True, batch=False):
+    print(f"[case] {label}", flush=True)
+    p = params or ff.Params()
+    g = run_gpu(ctx, frame, p, with_rgb=with_rgb, batch=batch)
+    o = O.fuse_frame(frame, oracle_params(p), with_rgb=with_rgb)
+    compare(g, o, label=label)
+    return g, o
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_configs_full(ctx, ff, name):
+    _case(ctx, ff, cached_frame(name), name)
+
+
+def test_c3_full(ctx, ff):
+    g, o = _case(ctx, ff, cached_frame("c3"), "c3")
+    assert g["info"][0] == len(o["member_ids"])          # M
+    assert g["info"][2] == (o["reps"] != O.PAD).sum()    # R
+
+
+@pytest.mark.parametrize("flags", [1, 2, 3, 4, 5])
+def test_ablation_flags(ctx, ff, flags):
+    _case(ctx, ff, cached_frame("c1"), f"c1 flags={flags}", ff.Params(flags=flags))
+
+
+@pytest.mark.parametrize("kw", [dict(k_views=1), dict(k_views=2), dict(k_views=8),
+                                dict(level_override=0), dict(level_override=6),
+                                dict(coarse_res=16), dict(coarse_res=128, max_level=4),
+                                dict(target_per_cell=1), dict(sigma=0.5, tau=0.8),
+                                dict(coarse_res=1, max_level=10)])
+def test_parameter_variants(ctx, ff, kw):
+    _case(ctx, ff, cached_frame("c2"), f"c2 {kw}", ff.Params(**kw))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_small_rigs(ctx, ff, seed):
+    """Ragged sizes (not multiples of 4 or of the 4096-pixel tile), odd camera counts."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 6))
+    res = [(int(rng.integers(3, 300)), int(rng.integers(2, 200))) for _ in range(n)]
+    cams = ring_cameras(res, jitter_pos=0.2, jitter_target=0.3, rng=rng)
+    prims = _scene_c2(rng, cams)
+    f = make_frame(cams, prims, 9000 + seed, outlier_frac=0.05, conf_model="beta")
+    _case(ctx, ff, f, f"random rig {seed} {res}")
+
+
+def test_empty_and_single_pixel(ctx, ff):
+    cam = make_camera(37, 5, np.array([0.0, -3, 0]), np.zeros(3))
+    D = np.zeros((5, 37), np.float32)
+    C = np.ones((5, 37), np.float32)
+
+    class Fr:
+        cams, depth, conf, rgb = [cam], [D], [C], None
+    g, o = _case(ctx, ff, Fr, "empty frame", with_rgb=False)
+    assert g["count"] == 0
+    D[2, 11] = 2.0
+    C[2, 11] = 0.75
+    g, o = _case(ctx, ff, Fr, "single pixel", with_rgb=False)
+    assert g["count"] == 1 and g["weight"][0] == np.float32(0.75)
+
+
+def test_nonfinite_inputs(ctx, ff):
+    f = make_config("c1")
+    D = [d.copy() for d in f.depth]
+    C = [c.copy() for c in f.conf]
+    D[0][10, :50] = np.nan
+    D[0][11, :50] = np.inf
+    D[0][12, :50] = -1.0
+    C[1][20, :] = np.nan
+    C[1][21, :] = np.float32(0.6)          # exactly tau: excluded
+    D[1][22, :3] = np.float32(3e38)        # finite depth, far point
+
+    class Fr:
+        cams, depth, conf, rgb = f.cams, D, C, f.rgb
+    _case(ctx, ff, Fr, "non-finite inputs")
+
+
+def test_identity_fusion(ctx, ff):
+    rng = np.random.default_rng(1000)
+    cams = ring_cameras([(320, 240)] * 2)
+    prims = _scene_c1(rng, cams)
+    f = make_frame(cams[:1], prims, 1000, noise=False)
+    g, o = _case(ctx, ff, f, "identity", ff.Params(level_override=6))
+    assert g["n_members"].max() == 1
+
+
+def test_batch_equals_single(ctx, ff):
+    frames = [cached_frame("c1"), cached_frame("c2"), cached_frame("c1", frame=1)]
+    print("[case] batch of c1, c2, c1/1", flush=True)
+    devs = [ff.to_device(f) for f in frames]
+    outs = ctx.fuse_batch(devs, members=True)
+    for f, out in zip(frames, outs):
+        g = out.result()
+        o = O.fuse_frame(f)
+        compare(g, o, label="batched")
+        s = run_gpu(ctx, f)
+        for k in ("keys", "xyz", "weight", "reps", "n_members", "rgb", "member_ids"):
+            assert np.array_equal(g[k], s[k]), k
+
+
+@pytest.mark.skip(reason="the single persistent launch that runs every phase in one kernel "
+                  "did not finish on the device in two runs; it is compiled out "
+                  "(FF_EXPERIMENTAL_PERSISTENT) until its cause is shown on the CPU")
+def test_persistent_single_launch(ctx, ff):
+    raise AssertionError("not built")
+
+
+def test_deterministic_repeat(ctx, ff):
+    f = cached_frame("c2")
+    print("[case] repeat c2 x3", flush=True)
+    a = run_gpu(ctx, f)
+    for _ in range(2):
+        b = run_gpu(ctx, f)
+        for k in ("keys", "xyz", "weight", "reps", "n_members", "rgb", "member_ids"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_capacity_overflow_reported(ctx, ff):
+    import torch
+    f = cached_frame("c1")
+    print("[case] capacity overflow", flush=True)
+    dev = ff.to_device(f)
+    o = O.fuse_frame(f)
+    S = len(o["keys"])
+    out = ff.Output(S // 2, rgb=True)
+    ctx.fuse(dev["cams"], dev["depth"], dev["conf"], dev["rgb"], out=out)
+    g = out.result()
+    assert g["status"] == 1 and g["count"] == S
+    n = S // 2
+    assert np.array_equal(g["keys"], o["keys"][:n])
+    assert np.array_equal(g["reps"], o["reps"][:n])
+
+
+def test_unaligned_inputs(ctx, ff):
+    """Depth/confidence views that are not 16-byte aligned take the scalar load path."""
+    import torch
+    f = cached_frame("c1")
+    print("[case] unaligned views", flush=True)
+    dev = ff.to_device(f)
+    D = [torch.cat([torch.zeros(1, device="cuda"), d.reshape(-1)])[1:].view_as(d) for d in dev["depth"]]
+    C = [torch.cat([torch.zeros(1, device="cuda"), c.reshape(-1)])[1:].view_as(c) for c in dev["conf"]]
+    assert D[0].data_ptr() % 16 != 0
+    out = ctx.fuse(dev["cams"], D, C, dev["rgb"], members=True)
+    compare(out.result(), O.fuse_frame(f), label="unaligned")
+
+
+def test_bad_arguments_raise(ctx, ff):
+    import torch
+    f = cached_frame("c1")
+    dev = ff.to_device(f)
+    with pytest.raises(ValueError):
+        ctx.fuse(dev["cams"], [d.cpu() for d in dev["depth"]], dev["conf"])
+    with pytest.raises(ff.FuseFlowError):
+        ctx.fuse(dev["cams"], dev["depth"], dev["conf"], params=ff.Params(coarse_res=48))
+    with pytest.raises(ff.FuseFlowError):
+        ctx.fuse(dev["cams"], dev["depth"], dev["conf"], params=ff.Params(k_views=9))
+    small = ff.Context(max_pixels=1000, max_cameras=2)
+    with pytest.raises(ff.FuseFlowError):
+        small.fuse(dev["cams"], dev["depth"], dev["conf"])
+    small.close()

@@ -1,0 +1,133 @@
+"""GPU tests of the batched path and the continuous-batching server.
+
+Each frame's result must be identical alone (ff_fuse) and in the mix (batched with other
+rigs' frames, overlapping on several streams); the oracle pins the alone result.
+"""
+import numpy as np
+import pytest
+
+from oracle import core as O
+from tests.conftest import cached_frame
+from tests.gpu_helpers import compare
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("keys", "xyz", "weight", "reps", "n_members", "rgb")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2602_01035_amd as ff
+    return ff
+
+
+def _alone(ff, dev):
+    ctx = ff.Context(max_pixels=4_000_000, max_cameras=16)
+    r = ctx.fuse(dev["cams"], dev["depth"], dev["conf"], dev.get("rgb")).result()
+    ctx.close()
+    return r
+
+
+def _frames():
+    # three rigs with different camera counts and resolutions, two frames each
+    return [cached_frame("c1", frame=f, rig=r) for r in (0, 1) for f in (0, 1)] + \
+           [cached_frame("c2", frame=f) for f in (0, 1)]
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_batched_matches_alone_and_oracle(ff, use_graph):
+    print(f"[case] batch of 6 frames, graph={use_graph}", flush=True)
+    frames = _frames()
+    devs = [ff.to_device(f) for f in frames]
+    ctx = ff.Context(max_pixels=8_000_000, max_cameras=32, max_frames=8)
+    ctx.set_tuning(use_graph=use_graph)
+    for rep in range(3):                     # replays of the cached graph
+        outs = ctx.fuse_batch(devs)
+        for f, d, out in zip(frames, devs, outs):
+            g = out.result()
+            a = _alone(ff, d)
+            for k in KEYS:
+                assert np.array_equal(g[k], a[k]), (rep, k)
+    compare(outs[0].result(), O.fuse_frame(frames[0]), label="batched vs oracle")
+    ctx.close()
+
+
+@pytest.mark.parametrize("tuning", [dict(radix_bits=4, sort_items=4),
+                                    dict(radix_bits=6, sort_items=16),
+                                    dict(radix_bits=8, sort_items=8)])
+def test_tuning_does_not_change_results(ff, tuning):
+    print(f"[case] tuning {tuning}", flush=True)
+    f = cached_frame("c2")
+    d = ff.to_device(f)
+    ctx = ff.Context(max_pixels=2_000_000, max_cameras=8, max_frames=2)
+    ctx.set_tuning(**tuning)
+    g = ctx.fuse_batch([d])[0].result()
+    compare(g, O.fuse_frame(f), label=str(tuning))
+    ctx.close()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_server_results_same_alone_and_in_mix(ff, plain):
+    print(f"[case] server plain={plain}", flush=True)
+    frames = _frames()
+    devs = [ff.to_device(f) for f in frames]
+    alone = [_alone(ff, d) for d in devs]
+    srv = ff.Server(hbm_budget_bytes=2 << 30, lanes=2, max_batch_frames=4, plain=plain)
+    tickets, outs = [], []
+    for rep in range(2):
+        for i, d in enumerate(devs):
+            out = ff.Output(sum(c.width * c.height for c in d["cams"]), rgb=True)
+            # arrivals spread over 20 ms so that batches form and overlap
+            tickets.append(srv.submit(rig=i % 3, frame=d, out=out, arrival_s=srv.now() + 0.002 * i))
+            outs.append((i, out))
+    srv.drain()
+    for i, out in outs:
+        g = out.result()
+        for k in KEYS:
+            assert np.array_equal(g[k], alone[i][k]), (i, k)
+    st = srv.stats()
+    assert st["frames"] == len(outs) and st["p99_ms"] >= st["p50_ms"] > 0
+    if plain:
+        assert st["mean_batch_frames"] == 1.0
+    srv.close()
+
+
+def test_server_admission_by_footprint(ff):
+    print("[case] admission", flush=True)
+    with pytest.raises(ff.FuseFlowError) as e:
+        ff.Server(hbm_budget_bytes=64 << 10, lanes=2)          # not even one small frame
+    assert e.value.status == ff.FF_ERR_OOM
+    f = cached_frame("c2")                                     # 1.2 Mpx
+    d = ff.to_device(f)
+    srv = ff.Server(hbm_budget_bytes=24 << 20, lanes=1, max_batch_frames=2)
+    assert srv.lane_pixels < f.pixels
+    with pytest.raises(ff.FuseFlowError) as e:
+        srv.submit(0, d, ff.Output(16))
+    assert e.value.status == ff.FF_ERR_OOM
+    small = cached_frame("c1")
+    ds = ff.to_device(small)
+    out = ff.Output(small.pixels)
+    t = srv.submit(0, ds, out)
+    srv.wait(t)
+    assert srv.poll(t)
+    assert out.result()["count"] == len(O.fuse_frame(small)["keys"])
+    srv.close()
+
+
+def test_server_back_pressure(ff):
+    print("[case] back-pressure", flush=True)
+    small = cached_frame("c1")
+    ds = ff.to_device(small)
+    srv = ff.Server(hbm_budget_bytes=1 << 30, lanes=1, max_batch_frames=1, max_pending=2)
+    later = srv.now() + 0.5                                     # not yet arrived
+    outs = [ff.Output(small.pixels) for _ in range(3)]
+    srv.submit(0, ds, outs[0], arrival_s=later)
+    srv.submit(0, ds, outs[1], arrival_s=later)
+    with pytest.raises(ff.FuseFlowError) as e:
+        srv.submit(0, ds, outs[2], arrival_s=later)
+    assert e.value.status == ff.FF_ERR_BUSY
+    srv.drain()
+    assert srv.stats()["frames"] == 2
+    srv.close()
