@@ -130,8 +130,9 @@ typedef struct ff_context ff_context;
 
 /* Launch/tuning knobs of the device path (chosen by ff_autotune or set by hand). */
 typedef struct ff_tuning {
-    int32_t radix_bits;           /* digit width of the LSD radix sort: 4, 6 or 8 */
-    int32_t sort_items;           /* keys per thread per sort tile: 4, 8 or 16 */
+    int32_t radix_bits;           /* widest digit of the LSD radix sort, 6..10 (the key bits
+                                     are spread evenly over the fewest passes) */
+    int32_t sort_items;           /* keys per thread per sort tile: 8 or 16 */
     int32_t cells_block;          /* threads per block in the per-cell phase: 64..1024 */
     int32_t use_graph;            /* 1: ff_fuse_batch replays a cached HIP graph (default) */
 } ff_tuning;
@@ -175,8 +176,10 @@ ff_status ff_autotune(ff_context* ctx, int32_t n_frames, const ff_frame* frames,
 
 /* Per-kernel timing.  While enabled, ff_fuse brackets every kernel it launches with HIP
  * events on the call's stream (ff_fuse_batch then launches directly instead of replaying a
- * graph).  Slots: 0 prep, 1 back-project+AABB, 2 coarse histogram, 3..5 coarse scan,
- * 6 keys, 7 cell heads, 8 cells (top-3, consistency, fusion), 9 final, 16+k radix pass k. */
+ * graph).  Slots: 0 back-project + AABB partials, 1 per-frame reduce, 2 coarse histogram,
+ * 3..5 coarse scan, 6 keys, 10..12 cell heads, 13 cells (top-3, consistency, fusion),
+ * 14 final, 15 camera prep, 16 + 3k + {0, 1, 2}: radix pass k (tile histograms, scan,
+ * scatter). */
 #define FF_TRACE_SLOTS 32
 typedef struct ff_trace {
     double total_ms[FF_TRACE_SLOTS];   /* summed kernel time per slot */

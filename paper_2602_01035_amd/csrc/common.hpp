@@ -9,18 +9,20 @@ constexpr int kWave = 64;                // CDNA wavefront
 constexpr int kPxPerThread = 16;         // pixels per thread in the per-pixel phases
 constexpr int kPxTile = kBlock * kPxPerThread;   // 4096 pixels per tile (never spans cameras)
 constexpr int kScanTile = kBlock * 16;   // coarse cells per scan tile
-constexpr int kMaxPass = 16;             // radix passes (4-bit digits over 64-bit keys)
-constexpr int kMaxDigits = 256;          // 8-bit digits at most
+constexpr int kMaxPass = 16;             // radix passes
+constexpr int kMaxRadixBits = 10;        // widest radix digit
+constexpr int kMaxDigits = 1 << kMaxRadixBits;
 constexpr int kMaxK = 8;                 // view budget K (own camera included)
 constexpr int kMaxCamsPerFrame = 64;
 constexpr int kMaxBatchCams = 1024;
 constexpr int kMaxFrames = 64;
-constexpr int kMaxPhases = 40;
+constexpr int kRSlots = 16;              // spread counters for representatives per frame
+constexpr int kHashSlots = 2048;         // LDS hash of the coarse histogram
+constexpr int kLdsCams = 256;            // cameras staged in LDS by the per-cell phase
 constexpr int kEMin = -24, kEMax = 100;  // clamp of the coarse exponent
 constexpr uint32_t kPad = 0xFFFFFFFFu;
 
 // status bits the kernels raise in BatchState::error
-constexpr uint32_t kErrSpin = 1u;        // a bounded wait gave up (never expected)
 constexpr uint32_t kErrBounds = 2u;      // an index failed a defensive bounds check
 
 struct DevParams {
@@ -44,9 +46,27 @@ struct DevCam {
     uint32_t frame;           // frame index in the batch
     uint32_t rank;            // rank in its frame under (centre x, y, z, index) (device)
     uint32_t vec_ok;          // depth and conf 16-byte aligned
+    uint32_t tab_off;         // first entry of this camera's ray tables (x then y)
+    uint32_t pad0;
     const float* depth;
     const float* conf;
     const uint8_t* rgb;
+};
+
+// the camera fields the per-cell phase needs, staged in LDS there
+struct CamLite {
+    float R[9];
+    float t[3];
+    float c[3];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    uint32_t rank, pix_off;
+    float invW;              // 1 / W, for a quick first guess of y = pixel / W
+    const float* depth;
+    const float* conf;
+    const uint8_t* rgb;
+    const float* rx;         // (x - cx) / fx for every column
+    const float* ry;         // (y - cy) / fy for every row
 };
 
 struct DevFrame {
@@ -74,32 +94,44 @@ struct CallHdr {
     uint32_t n_frames, n_cams;
     uint32_t n_px_tiles, P_tot;
     uint32_t n_scan_tiles, n_sort_tiles;
-    uint32_t n_cell_items, radix_bits;
-    uint32_t npass_max, n_phases;
-    uint64_t wait_ticks;                    // wall-clock bound of any single wait
-    uint32_t phase_begin[kMaxPhases + 1];   // persistent schedule: first ticket of each phase
-    uint32_t phase_kind[kMaxPhases];
+    uint32_t n_cell_items, max_radix_bits;
+    uint32_t npass_max, n_counts;
+    uint32_t sort_items, lds_cams;
+};
+
+// per pixel tile: AABB partial (order-preserving encodings) and gated count
+struct TilePart {
+    uint32_t mn[3], mx[3];
+    uint32_t cnt, pad;
 };
 
 struct FrameState {
-    uint32_t bmin_o[3], bmax_o[3];   // order-preserving encodings of the AABB
-    uint32_t M, S, R, pad;
+    uint32_t bmin_o[3], bmax_o[3];   // AABB (order-preserving encodings)
+    float bmin[3];                   // AABB minimum
+    float scale;                     // 2^-e, e the coarse exponent
+    int32_t e;
+    uint32_t M;                      // gated points
+    uint32_t key_begin;              // first compacted/sorted position of the frame
+    uint32_t cell_begin;             // first global cell of the frame
+    uint32_t has_cells;
+    uint32_t pad[3];
     uint64_t fine_begin;             // first dense fine index of the frame
+    uint32_t R[kRSlots];             // representatives (spread counters, summed at the end)
 };
 
 struct BatchState {
-    uint32_t tickets[kMaxPhases];
-    uint32_t done[kMaxPhases];
     uint32_t M_tot, S_tot, error, key64;
     uint32_t key_bits, npass, pad0, pad1;
     uint64_t T_tot;
-    uint32_t digit_hist[kMaxPass][kMaxDigits];
+    uint32_t pass_shift[kMaxPass];
+    uint32_t pass_bits[kMaxPass];
 };
 
 enum PhaseKind : uint32_t {
-    PH_BACKPROJECT = 0, PH_HIST = 1, PH_SCAN_A = 2, PH_SCAN_M = 3, PH_SCAN_B = 4,
-    PH_KEYS = 5, PH_HEADS = 6, PH_CELLS = 7, PH_FINAL = 8,
-    PH_RADIX = 16      // + pass index
+    PH_BACKPROJECT = 0, PH_TILE_REDUCE = 1, PH_HIST = 2, PH_SCAN_A = 3, PH_SCAN_M = 4,
+    PH_SCAN_B = 5, PH_KEYS = 6, PH_RADIX_UP = 7, PH_RADIX_SCAN = 8, PH_RADIX_DOWN = 9,
+    PH_HEAD_COUNT = 10, PH_HEAD_SCAN = 11, PH_HEAD_WRITE = 12, PH_CELLS = 13, PH_FINAL = 14,
+    PH_CAM_PREP = 15, PH_COUNT = 16
 };
 
 }  // namespace ff

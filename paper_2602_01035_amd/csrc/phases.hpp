@@ -1,15 +1,18 @@
 // Device phases of the fusion path for gfx950 (wave64, CDNA4).
 //
-// Each phase is a function of one work item (a tile of pixels, keys or cells).  The same
-// functions run either as one kernel per phase (ff_fuse) or inside one persistent kernel
-// that walks a global ticket space phase by phase (ff_fuse_batch).  Determinism: only
-// integer atomics are used (histograms, counters); every floating-point reduction has a
-// fixed order; compaction and sorting are stable, so members keep pixel-id order.
+// Each phase is a function of one work item (a tile of pixels, keys or cells); the host
+// launches one kernel per phase with one workgroup per item.  Design rules for MI355X:
+//  * no same-address global atomics (they serialise at the memory side): per-tile partials
+//    are written with plain stores and reduced by a small phase;
+//  * no decoupled look-back (each step would be a coherent cross-XCD load of ~1-2 us):
+//    compactions and the radix sort use counts + scan + scatter;
+//  * only integer atomics, so every result is deterministic; compaction and the LSD radix
+//    sort are stable, so the members of a cell keep pixel-id order.
 //
-// Paper map: Eq. 8-9 -> backproject/gate; Sec. II.5(1) b-e -> AABB, coarse histogram,
-// level selection, keys; the spatial hash grouping -> LSD radix sort of dense cell
-// indices; Sec. II.5(2) a -> top-3 per cell; II.5(2) b and Eq. 4-7 -> view selection and
-// consistency; Eq. 10-11 -> joint weight and fusion.
+// Paper map: Eq. 8-9 -> backproject / gate; Sec. II.5(1) b-e -> extents, coarse density,
+// level selection, cell keys; the spatial hash grouping -> LSD radix sort of dense cell
+// indices + segment heads; Sec. II.5(2) a -> top-3 per cell; II.5(2) b and Eq. 4-7 -> view
+// selection and distance consistency; Eq. 10-11 -> joint weight and fusion.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -23,6 +26,8 @@ struct Ctx {
     DevCam* cams;
     BatchState* bs;
     FrameState* fs;
+    TilePart* tiles;         // [n_px_tiles] AABB partials and gated counts
+    uint32_t* tile_off;      // [n_px_tiles] first compacted position of each pixel tile
     uint32_t* counts;        // [F][G^3] gated points per coarse cell
     uint64_t* fine_base;     // [F][G^3] first dense fine index of each coarse cell
     uint64_t* scan_tile;     // [n_scan_tiles] tile sums, then exclusive prefixes
@@ -30,15 +35,27 @@ struct Ctx {
     void* keysB;
     uint32_t* valsA;         // batch pixel ids
     uint32_t* valsB;
+    uint32_t* digit_hist;    // [kMaxDigits][n_sort_tiles] per-tile digit counts / offsets
+    uint32_t* digit_total;   // [kMaxDigits]
+    uint32_t* head_cnt;      // [n_sort_tiles] cell heads per sort tile, then offsets
     uint32_t* cell_start;    // [S + 1] first sorted position of each cell
-    uint64_t* lb_tile;       // look-back words per tile (compactions)
-    uint64_t* lb_digit;      // look-back words per (sort tile, digit)
-    const uint32_t* epoch;
-    uint32_t P_cap;          // entries of keys/vals/cell_start - 1
-    uint32_t lb_tile_cap, lb_digit_cap;
+    uint32_t* conf_sorted;   // [M] confidence bits of each key in sorted order
+    CamLite* camlite;        // [n_cams]
+    float* raytab;           // per camera: (x - cx)/fx for each column, (y - cy)/fy per row
+    uint32_t P_cap;          // entries of keys/vals (cell_start has P_cap + 2)
+    uint32_t sort_tiles_cap;
 };
 
 // ---------------------------------------------------------------- small device helpers
+
+// Pointers read out of descriptors are generic to the compiler: accessed as such they
+// compile to flat instructions, which also count against the LDS wait counter and so
+// serialise LDS reads behind outstanding global loads.  Every descriptor pointer refers to
+// device global memory, which glob() states.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glob(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -48,35 +65,6 @@ __device__ __forceinline__ uint32_t f2o(float f) {
 }
 __device__ __forceinline__ float o2f(uint32_t o) {
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
-}
-
-template <typename T>
-__device__ __forceinline__ T ld_relaxed(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void st_relaxed(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Every wait is bounded by wall-clock time (s_memrealtime ticks, limit in the call header)
-// and gives up at once when another wait already gave up.
-struct Waiter {
-    uint64_t t0, limit;
-    uint32_t n;
-    __device__ __forceinline__ explicit Waiter(uint64_t lim) : t0(wall_clock64()), limit(lim), n(0) {}
-    // true when the wait must stop
-    __device__ __forceinline__ bool expired(BatchState* bs);
-};
-
-// true once any bounded wait has given up: every later wait returns at once, so a logic
-// error can never turn into a long chain of timed-out waits
-__device__ __forceinline__ bool aborted(BatchState* bs) {
-    return ld_relaxed(&bs->error) & kErrSpin;
-}
-__device__ __forceinline__ bool Waiter::expired(BatchState* bs) {
-    if ((++n & 31u) != 0) return false;
-    return aborted(bs) || (wall_clock64() - t0) > limit;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -142,80 +130,25 @@ __device__ __forceinline__ uint64_t block_excl64(uint64_t v, uint64_t* s_w, uint
     total = tot;
     return off + inc - v;
 }
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* s_w) {
+    uint32_t tot;
+    (void)block_excl(v, s_w, tot);
+    return tot;
+}
 
 __device__ __forceinline__ void raise_error(BatchState* bs, uint32_t bit) {
     atomicOr(&bs->error, bit);
 }
 
-// Look-back word: high 32 bits = (tag << 2) | flag, low 32 bits = value.
-// flag 1 = tile aggregate, 2 = inclusive prefix.
-__device__ __forceinline__ uint64_t lb_word(uint32_t tag, uint32_t flag, uint32_t v) {
-    return ((uint64_t)((tag << 2) | flag) << 32) | v;
-}
-__device__ __forceinline__ uint32_t lb_tag(uint32_t epoch, uint32_t slot) {
-    return ((epoch << 5) | slot) & 0x3FFFFFFFu;
-}
-
-// Exclusive prefix of `tile` over earlier tiles (decoupled look-back, one wave, 64
-// predecessors per step).  Every earlier tile was claimed by a running workgroup before
-// this one (tickets), so each wait ends; a bounded spin guards against logic errors.
-__device__ uint32_t lookback_wave(uint64_t* lb, uint32_t tile, uint32_t tag, BatchState* bs,
-                                  uint64_t wait_ticks) {
-    const uint32_t l = lane_id();
-    Waiter wt(wait_ticks);
-    uint32_t prefix = 0;
-    int64_t base = (int64_t)tile - 1;
-    while (base >= 0) {
-        const int64_t idx = base - (int64_t)l;
-        uint64_t w = 0;
-        bool ready = idx < 0;
-        while (true) {
-            if (!ready) {
-                w = ld_relaxed(&lb[idx]);
-                const uint32_t hi = (uint32_t)(w >> 32);
-                ready = ((hi >> 2) == tag) && (hi & 3u);
-            }
-            if (__all(ready)) break;
-            if (wt.expired(bs)) {
-                if (l == 0) raise_error(bs, kErrSpin);
-                return prefix;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        const uint32_t hi = (uint32_t)(w >> 32);
-        const uint32_t flag = idx < 0 ? 2u : (hi & 3u);
-        const uint32_t val = idx < 0 ? 0u : (uint32_t)w;
-        const uint64_t pm = __ballot(flag == 2u);
-        const uint32_t first = pm ? (uint32_t)(__ffsll((unsigned long long)pm) - 1) : 64u;
-        prefix += wave_sum(l <= first ? val : 0u);
-        if (pm) break;
-        base -= kWave;
+// Lanes of the wave holding the same value `d` among the active ones of `valid`, using
+// one ballot per bit of a `bits`-wide value.
+__device__ __forceinline__ uint64_t match_peers(uint32_t d, bool valid, uint32_t bits) {
+    uint64_t peers = __ballot(valid);
+    for (uint32_t b = 0; b < bits; ++b) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? bal : ~bal;
     }
-    return prefix;
-}
-
-// Single-thread look-back (one digit per thread in the radix passes).
-__device__ uint32_t lookback_thread(uint64_t* lb, uint32_t tile, uint32_t stride, uint32_t d,
-                                    uint32_t tag, BatchState* bs, uint64_t wait_ticks) {
-    uint32_t prefix = 0;
-    Waiter wt(wait_ticks);
-    for (int64_t t = (int64_t)tile - 1; t >= 0; --t) {
-        uint64_t w;
-        uint32_t hi;
-        while (true) {
-            w = ld_relaxed(&lb[(uint64_t)t * stride + d]);
-            hi = (uint32_t)(w >> 32);
-            if (((hi >> 2) == tag) && (hi & 3u)) break;
-            if (wt.expired(bs)) {
-                raise_error(bs, kErrSpin);
-                return prefix;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        prefix += (uint32_t)w;
-        if ((hi & 3u) == 2u) break;
-    }
-    return prefix;
+    return peers;
 }
 
 // ---------------------------------------------------------------- the method's arithmetic
@@ -226,7 +159,20 @@ struct Pt {
 };
 
 // Eq. 8: camera-frame point (d (x - cx)/fx, d (y - cy)/fy, d), then R^T X + c.
-__device__ __forceinline__ Pt backproject(const DevCam& cm, float fxp, float fyp, float d) {
+// The same with the normalised ray (xn, yn) = ((x - cx)/fx, (y - cy)/fy) already divided
+// out (per-camera tables hold exactly these float32 quotients).
+template <typename Cam>
+__device__ __forceinline__ Pt backproject_ray(const Cam& cm, float xn, float yn, float d) {
+    const float X = xn * d, Y = yn * d, Z = d;
+    Pt p;
+    p.x = ((cm.R[0] * X + cm.R[3] * Y) + cm.R[6] * Z) + cm.c[0];
+    p.y = ((cm.R[1] * X + cm.R[4] * Y) + cm.R[7] * Z) + cm.c[1];
+    p.z = ((cm.R[2] * X + cm.R[5] * Y) + cm.R[8] * Z) + cm.c[2];
+    return p;
+}
+
+template <typename Cam>
+__device__ __forceinline__ Pt backproject(const Cam& cm, float fxp, float fyp, float d) {
     const float xn = (fxp - cm.cx) / cm.fx;
     const float yn = (fyp - cm.cy) / cm.fy;
     const float X = xn * d, Y = yn * d, Z = d;
@@ -246,7 +192,8 @@ __device__ __forceinline__ bool finite3(const Pt& p) {
 }
 
 // Eq. 4: nearest pixel of the projection into camera cm; false when behind or outside.
-__device__ __forceinline__ bool project(const DevCam& cm, const Pt& p, int& px, int& py) {
+template <typename Cam>
+__device__ __forceinline__ bool project(const Cam& cm, const Pt& p, int& px, int& py) {
     const float X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
     const float Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
     const float Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
@@ -258,6 +205,39 @@ __device__ __forceinline__ bool project(const DevCam& cm, const Pt& p, int& px, 
     px = ok ? (int)fu : 0;
     py = ok ? (int)fv : 0;
     return ok;
+}
+
+// Eq. 4 FOV decision with the division only where it matters: an approximate reciprocal
+// decides points that are clearly inside or outside the image (the margin dwarfs its
+// error), and the exact IEEE quotients are computed near the borders.  Returns the same
+// decision as project(); px, py are valid only when exact is set.
+template <typename Cam>
+__device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p, float& X, float& Y,
+                                             float& Z) {
+    X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
+    Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
+    Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
+    if (!(Z > 0.0f)) return false;
+    const float rz = __builtin_amdgcn_rcpf(Z);
+    const float ta = cm.fx * (X * rz) + cm.cx + 0.5f;
+    const float tb = cm.fy * (Y * rz) + cm.cy + 0.5f;
+    const float W = (float)cm.W, H = (float)cm.H, m = 0.0625f;
+    const bool sure_in = ta >= m && ta < W - m && tb >= m && tb < H - m;
+    const bool sure_out = !(ta >= -m && ta < W + m && tb >= -m && tb < H + m);
+    if (sure_in) return true;
+    if (sure_out) return false;
+    const float u = cm.fx * (X / Z) + cm.cx, v = cm.fy * (Y / Z) + cm.cy;
+    const float fu = floorf(u + 0.5f), fv = floorf(v + 0.5f);
+    return (fu >= 0.0f) && (fu < W) && (fv >= 0.0f) && (fv < H);
+}
+
+// exact nearest pixel of a point known to be in view (same arithmetic as project())
+template <typename Cam>
+__device__ __forceinline__ void exact_pixel(const Cam& cm, float X, float Y, float Z, int& px,
+                                            int& py) {
+    const float u = cm.fx * (X / Z) + cm.cx, v = cm.fy * (Y / Z) + cm.cy;
+    px = (int)floorf(u + 0.5f);
+    py = (int)floorf(v + 0.5f);
 }
 
 // Sec. II.5(1)c: coarse edge 2^e, smallest power of two with G 2^e >= longest extent.
@@ -293,22 +273,15 @@ __device__ __forceinline__ int level_of(uint32_t n, const DevParams& P) {
 struct FrameGrid {
     float bmin[3];
     float scale;      // 2^-e
-    int G, log2G;
+    int G;
 };
 
 __device__ __forceinline__ void frame_grid(const FrameState& st, const DevParams& P,
                                            FrameGrid& g) {
-    float lo[3], hi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = o2f(st.bmin_o[a]);
-        hi[a] = o2f(st.bmax_o[a]);
-        g.bmin[a] = lo[a];
-    }
-    const int e = coarse_exponent(lo, hi, P.log2G);
-    g.scale = __uint_as_float((uint32_t)(127 - e) << 23);
+    for (int a = 0; a < 3; ++a) g.bmin[a] = st.bmin[a];
+    g.scale = st.scale;
     g.G = P.G;
-    g.log2G = P.log2G;
 }
 
 struct CellCoord {
@@ -362,21 +335,29 @@ __device__ __forceinline__ int cam_of_tile(const Ctx& C, uint32_t tile) {
     return lo;
 }
 
-// camera owning batch pixel id (pix_off table staged in LDS)
-__device__ __forceinline__ int cam_of_pix(const uint32_t* s_off, int n, uint32_t id) {
+// index of the last entry <= id in an ascending table (camera or frame pixel offsets)
+__device__ __forceinline__ int last_le(const uint32_t* tab, int n, uint32_t id) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= id) lo = mid; else hi = mid - 1;
+        if (tab[mid] <= id) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// camera centre c = -R^T t in the canonical order (Eq. 8's inverse extrinsics)
+__device__ __forceinline__ void camera_centre(DevCam& cm) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        cm.c[a] = -((cm.R[0 * 3 + a] * cm.t[0] + cm.R[1 * 3 + a] * cm.t[1]) +
+                    cm.R[2 * 3 + a] * cm.t[2]);
 }
 
 // ---------------------------------------------------------------- per-pixel tile walk
 
 // Visit the 16 pixels of this thread in tile `tile` (4 groups of 4 consecutive pixels, the
 // groups 1024 pixels apart, so that a wave reads 1 KiB contiguous per load).  f(g, j, x, y,
-// d, c, in_range) is called in pixel order for each thread.
+// d, c, in_range, index) is called in pixel order for each thread.
 template <typename F>
 __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile, F&& f) {
     const uint32_t npx = (uint32_t)cm.W * (uint32_t)cm.H;
@@ -387,16 +368,17 @@ __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile,
         const uint32_t idx = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
         float d[4], c[4];
         if (cm.vec_ok && idx + 3 < npx) {
-            const float4 dv = *reinterpret_cast<const float4*>(cm.depth + idx);
-            const float4 cv = *reinterpret_cast<const float4*>(cm.conf + idx);
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 dv = *glob(reinterpret_cast<const f4*>(cm.depth + idx));
+            const f4 cv = *glob(reinterpret_cast<const f4*>(cm.conf + idx));
             d[0] = dv.x; d[1] = dv.y; d[2] = dv.z; d[3] = dv.w;
             c[0] = cv.x; c[1] = cv.y; c[2] = cv.z; c[3] = cv.w;
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bool in = idx + j < npx;
-                d[j] = in ? cm.depth[idx + j] : 0.0f;
-                c[j] = in ? cm.conf[idx + j] : 0.0f;
+                d[j] = in ? glob(cm.depth)[idx + j] : 0.0f;
+                c[j] = in ? glob(cm.conf)[idx + j] : 0.0f;
             }
         }
         uint32_t y = idx / W;
@@ -409,19 +391,74 @@ __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile,
     }
 }
 
-// ---------------------------------------------------------------- phase: back-project + AABB
+// ---------------------------------------------------------------- phase: camera prep
+// One workgroup per camera: the centre c = -R^T t (Eq. 8's inverse extrinsics), the rank
+// of the camera in its frame under (centre x, y, z, index) used to break distance ties,
+// the staged copy used by the per-cell phase, and the ray tables (x - cx)/fx per column
+// and (y - cy)/fy per row, so that no per-pixel step divides.
 
-__device__ void ph_backproject(const Ctx& C, uint32_t tile, char* smem) {
+__device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem) {
+    DevCam& cm = C.cams[i];
+    const DevFrame& fr = C.frames[cm.frame];
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
+    DevCam me = cm;
+    camera_centre(me);
+    // rank: count the frame's cameras that come first
+    uint32_t before = 0;
+    for (uint32_t j = fr.cam_begin + threadIdx.x; j < fr.cam_begin + fr.n_cams; j += kBlock) {
+        DevCam o = C.cams[j];
+        camera_centre(o);
+        bool b;
+        if (o.c[0] != me.c[0]) b = o.c[0] < me.c[0];
+        else if (o.c[1] != me.c[1]) b = o.c[1] < me.c[1];
+        else if (o.c[2] != me.c[2]) b = o.c[2] < me.c[2];
+        else b = j < i;
+        before += b ? 1u : 0u;
+    }
+    const uint32_t rank = block_sum(before, s_w);
+    float* rx = C.raytab + cm.tab_off;
+    float* ry = rx + cm.W;
+    for (int x = threadIdx.x; x < cm.W; x += kBlock) rx[x] = ((float)x - me.cx) / me.fx;
+    for (int y = threadIdx.x; y < cm.H; y += kBlock) ry[y] = ((float)y - me.cy) / me.fy;
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) cm.c[a] = me.c[a];
+        cm.rank = rank;
+        CamLite cl;
+        for (int a = 0; a < 9; ++a) cl.R[a] = me.R[a];
+        for (int a = 0; a < 3; ++a) { cl.t[a] = me.t[a]; cl.c[a] = me.c[a]; }
+        cl.fx = me.fx; cl.fy = me.fy; cl.cx = me.cx; cl.cy = me.cy;
+        cl.W = me.W; cl.H = me.H; cl.rank = rank; cl.pix_off = me.pix_off;
+        cl.invW = 1.0f / (float)me.W;
+        cl.depth = me.depth; cl.conf = me.conf; cl.rgb = me.rgb;
+        cl.rx = rx;
+        cl.ry = ry;
+        C.camlite[i] = cl;
+    }
+}
+
+// ---------------------------------------------------------------- phase: back-project + AABB
+// Eq. 8-9 per pixel, and the extents of Sec. II.5(1)b as per-tile partials (no atomics).
+// Also clears this tile's share of the coarse histogram for the next phases.
+
+__device__ __forceinline__ void ph_backproject(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
-    const int ci = cam_of_tile(C, tile);
-    const DevCam& cm = C.cams[ci];
+    const uint32_t tid = threadIdx.x;
+    if (!(P.flags & 4u)) {
+        const uint32_t nc = H.n_counts;
+        const uint32_t chunk = (nc + H.n_px_tiles - 1) / H.n_px_tiles;
+        const uint32_t b0 = tile * chunk, b1 = min(nc, b0 + chunk);
+        for (uint32_t i = b0 + tid; i < b1; i += kBlock) C.counts[i] = 0;
+    }
+    const DevCam& cm = C.cams[cam_of_tile(C, tile)];
+    const float* rx = C.raytab + cm.tab_off;
+    const float* ry = rx + cm.W;
     const bool no_mf = P.flags & 1u;
     uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u}, cnt = 0;
     for_tile_pixels(cm, tile, [&](int, int, uint32_t x, uint32_t y, float d, float c, bool in,
                                   uint32_t) {
         if (!in || !gate_px(d, c, P.tau, no_mf)) return;
-        const Pt p = backproject(cm, (float)x, (float)y, d);
+        const Pt p = backproject_ray(cm, rx[x], ry[y], d);
         if (!finite3(p)) return;
         const uint32_t o[3] = {f2o(p.x), f2o(p.y), f2o(p.z)};
 #pragma unroll
@@ -431,7 +468,6 @@ __device__ void ph_backproject(const Ctx& C, uint32_t tile, char* smem) {
         }
         ++cnt;
     });
-    // wave reduce, then one atomic per wave (integer, order-independent)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
 #pragma unroll
@@ -442,63 +478,199 @@ __device__ void ph_backproject(const Ctx& C, uint32_t tile, char* smem) {
         }
         cnt += __shfl_xor(cnt, o);
     }
-    if (lane_id() == 0 && cnt) {
-        FrameState& st = C.fs[cm.frame];
-#pragma unroll
+    uint32_t* s = reinterpret_cast<uint32_t*>(smem);     // [4][8]
+    const uint32_t w = tid / kWave;
+    if (lane_id() == 0) {
+        for (int a = 0; a < 3; ++a) { s[w * 8 + a] = mn[a]; s[w * 8 + 3 + a] = mx[a]; }
+        s[w * 8 + 6] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        TilePart tp;
         for (int a = 0; a < 3; ++a) {
-            atomicMin(&st.bmin_o[a], mn[a]);
-            atomicMax(&st.bmax_o[a], mx[a]);
+            tp.mn[a] = min(min(s[a], s[8 + a]), min(s[16 + a], s[24 + a]));
+            tp.mx[a] = max(max(s[3 + a], s[11 + a]), max(s[19 + a], s[27 + a]));
         }
-        atomicAdd(&st.M, cnt);
+        tp.cnt = s[6] + s[14] + s[22] + s[30];
+        tp.pad = 0;
+        C.tiles[tile] = tp;
     }
 }
 
-// ---------------------------------------------------------------- phase: coarse histogram
+// ---------------------------------------------------------------- phase: per-frame reduce
+// One workgroup: per-frame AABB, point count and coarse grid (Sec. II.5(1)b-c), the
+// compaction offset of every pixel tile, camera centres and their tie-break ranks.
 
-__device__ void ph_hist(const Ctx& C, uint32_t tile, char* smem) {
+__device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
-    const int ci = cam_of_tile(C, tile);
-    const DevCam& cm = C.cams[ci];
+    const uint32_t tid = threadIdx.x, w = tid / kWave;
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);          // [8]
+    uint32_t* s_r = s_w + 8;                                    // [4][8]
+    BatchState& bs = *C.bs;
+    if (tid == 0) {
+        bs.M_tot = 0; bs.S_tot = 0; bs.error = 0; bs.key64 = 0;
+        bs.key_bits = 0; bs.npass = 0; bs.T_tot = 0;
+    }
+    uint32_t carry = 0;
+    for (uint32_t f = 0; f < H.n_frames; ++f) {
+        const DevFrame& fr = C.frames[f];
+        uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
+        const uint32_t key_begin = carry;
+        for (uint32_t b = 0; b < fr.n_tiles; b += kBlock) {
+            const uint32_t t = fr.tile_begin + b + tid;
+            const bool in = b + tid < fr.n_tiles;
+            TilePart tp;
+            if (in) tp = C.tiles[t];
+            const uint32_t c = in ? tp.cnt : 0u;
+            if (in && c) {
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = min(mn[a], tp.mn[a]);
+                    mx[a] = max(mx[a], tp.mx[a]);
+                }
+            }
+            uint32_t tot;
+            const uint32_t ex = block_excl(c, s_w, tot);
+            if (in) C.tile_off[t] = carry + ex;
+            carry += tot;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = min(mn[a], (uint32_t)__shfl_xor(mn[a], o));
+                mx[a] = max(mx[a], (uint32_t)__shfl_xor(mx[a], o));
+            }
+        }
+        if (lane_id() == 0)
+            for (int a = 0; a < 3; ++a) { s_r[w * 8 + a] = mn[a]; s_r[w * 8 + 3 + a] = mx[a]; }
+        __syncthreads();
+        if (tid == 0) {
+            FrameState& st = C.fs[f];
+            float lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                st.bmin_o[a] = min(min(s_r[a], s_r[8 + a]), min(s_r[16 + a], s_r[24 + a]));
+                st.bmax_o[a] = max(max(s_r[3 + a], s_r[11 + a]), max(s_r[19 + a], s_r[27 + a]));
+                lo[a] = o2f(st.bmin_o[a]);
+                hi[a] = o2f(st.bmax_o[a]);
+                st.bmin[a] = lo[a];
+            }
+            st.e = coarse_exponent(lo, hi, P.log2G);
+            st.scale = __uint_as_float((uint32_t)(127 - st.e) << 23);
+            st.M = carry - key_begin;
+            st.key_begin = key_begin;
+            st.cell_begin = 0;
+            st.has_cells = 0;
+            st.fine_begin = 0;
+            for (int k = 0; k < kRSlots; ++k) st.R[k] = 0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) bs.M_tot = carry;
+}
+
+// ---------------------------------------------------------------- phase: coarse histogram
+// Sec. II.5(1)c.  Lanes of a wave with the same coarse cell are merged (one ballot per
+// round), the wave leaders accumulate into an LDS hash of the tile's cells, and one global
+// atomic per distinct cell and tile goes out at the end.
+
+__device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t tile, char* smem) {
+    const CallHdr& H = *C.hdr;
+    const DevParams& P = H.prm;
+    if (P.flags & 4u) return;
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* s_cnt = s_key + kHashSlots;
+    for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
+        s_key[i] = kPad;
+        s_cnt[i] = 0;
+    }
+    __syncthreads();
+    const DevCam& cm = C.cams[cam_of_tile(C, tile)];
+    const float* rx = C.raytab + cm.tab_off;
+    const float* ry = rx + cm.W;
     const bool no_mf = P.flags & 1u;
     FrameGrid g;
     frame_grid(C.fs[cm.frame], P, g);
     uint32_t* counts = C.counts + (uint64_t)cm.frame * (uint64_t)(P.G * P.G * P.G);
-    for_tile_pixels(cm, tile, [&](int, int, uint32_t x, uint32_t y, float d, float c, bool in,
-                                  uint32_t) {
-        bool has = in && gate_px(d, c, P.tau, no_mf);
-        uint32_t key = 0;
-        if (has) {
-            const Pt p = backproject(cm, (float)x, (float)y, d);
-            has = finite3(p);
-            if (has) key = coarse_cell(g, p).lin;
-        }
-        // wavefront-level histogram: one atomic per distinct coarse cell in the wave
+    // merge the lanes holding the same cell (one ballot per round); the leader adds the
+    // summed count to the tile's LDS hash (global atomic if the hash is full)
+    auto insert = [&](uint32_t key, uint32_t n, bool has) {
         uint64_t pending = __ballot(has);
         while (pending) {
             const int leader = __ffsll((unsigned long long)pending) - 1;
             const uint32_t lk = __shfl(key, leader);
-            const uint64_t peers = __ballot(has && key == lk);
-            if ((int)lane_id() == leader) atomicAdd(&counts[lk], (uint32_t)__popcll(peers));
+            const bool peer = has && key == lk;
+            const uint64_t peers = __ballot(peer);
+            const uint32_t tot = wave_sum(peer ? n : 0u);
+            if ((int)lane_id() == leader) {
+                uint32_t h = (lk * 2654435761u) >> (32 - 11);
+                bool done = false;
+                for (int probe = 0; probe < 32 && !done; ++probe) {
+                    const uint32_t old = atomicCAS(&s_key[h], kPad, lk);
+                    if (old == kPad || old == lk) {
+                        atomicAdd(&s_cnt[h], tot);
+                        done = true;
+                    } else {
+                        h = (h + 1) & (kHashSlots - 1);
+                    }
+                }
+                if (!done) atomicAdd(&counts[lk], tot);
+            }
             pending &= ~peers;
-            if (key == lk) has = false;
+            if (peer) has = false;
+        }
+    };
+    uint32_t kk[4];
+    bool hv[4];
+    for_tile_pixels(cm, tile, [&](int, int j, uint32_t x, uint32_t y, float d, float c, bool in,
+                                  uint32_t) {
+        bool has = in && gate_px(d, c, P.tau, no_mf);
+        uint32_t key = 0;
+        if (has) {
+            const Pt p = backproject_ray(cm, rx[x], ry[y], d);
+            has = finite3(p);
+            if (has) key = coarse_cell(g, p).lin;
+        }
+        kk[j] = key;
+        hv[j] = has;
+        if (j == 3) {
+            // a thread's 4 neighbouring pixels nearly always share their coarse cell:
+            // merge them first, then the rare others one by one
+            uint32_t k0 = 0, n0 = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (hv[q] && (n0 == 0 || kk[q] == k0)) {
+                    k0 = kk[q];
+                    ++n0;
+                    hv[q] = false;
+                }
+            }
+            insert(k0, n0, n0 > 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) insert(kk[q], 1u, hv[q]);
         }
     });
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
+        const uint32_t k = s_key[i];
+        if (k != kPad) atomicAdd(&counts[k], s_cnt[i]);
+    }
 }
 
 // ---------------------------------------------------------------- phase: coarse scan
-// span(c) = 8^L(c) dense fine indices for every occupied coarse cell; exclusive scan over
-// (frame, cell) gives each cell's first dense index.  Three sub-phases: tile sums, a
-// one-workgroup scan of the tile sums, and the per-tile scan.
+// span(c) = 8^L(c) dense fine indices for every occupied coarse cell; the exclusive scan
+// over (frame, cell) gives each cell's first dense index.  Three steps: tile sums, a
+// one-workgroup scan of the tile sums (which also fixes the sort's key width and passes),
+// and the per-tile scan.
 
 __device__ __forceinline__ uint64_t span_of(uint32_t n, const DevParams& P) {
     return n ? (1ull << (3 * level_of(n, P))) : 0ull;
 }
 
-__device__ void ph_scan_a(const Ctx& C, uint32_t tile, char* smem) {
+__device__ __forceinline__ void ph_scan_a(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
-    const uint64_t total = (uint64_t)H.n_frames * (uint64_t)(P.G * P.G * P.G);
+    const uint64_t total = H.n_counts;
     uint64_t s = 0;
     const uint64_t base = (uint64_t)tile * kScanTile;
 #pragma unroll 4
@@ -513,7 +685,7 @@ __device__ void ph_scan_a(const Ctx& C, uint32_t tile, char* smem) {
     if (threadIdx.x == 0) C.scan_tile[tile] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-__device__ void ph_scan_m(const Ctx& C, uint32_t, char* smem) {
+__device__ __forceinline__ void ph_scan_m(const Ctx& C, uint32_t, char* smem) {
     const CallHdr& H = *C.hdr;
     const uint32_t n = H.n_scan_tiles;
     uint64_t* s_w = reinterpret_cast<uint64_t*>(smem);
@@ -532,21 +704,29 @@ __device__ void ph_scan_m(const Ctx& C, uint32_t, char* smem) {
         const uint32_t bits = carry > 1 ? 64u - (uint32_t)__clzll((long long)(carry - 1)) : 0u;
         bs.key_bits = bits;
         bs.key64 = bits > 32 ? 1u : 0u;
-        const uint32_t rb = H.radix_bits;
-        uint32_t np = (bits + rb - 1) / rb;
+        const uint32_t mb = H.max_radix_bits;
+        uint32_t np = (bits + mb - 1) / mb;
         if (np > H.npass_max) {           // cannot happen: npass_max bounds the key width
             raise_error(C.bs, kErrBounds);
             np = H.npass_max;
         }
         bs.npass = np;
+        // spread the key bits evenly over the passes (fewest passes, narrowest digits)
+        uint32_t shift = 0;
+        for (uint32_t k = 0; k < np; ++k) {
+            const uint32_t w = bits / np + (k < bits % np ? 1u : 0u);
+            bs.pass_shift[k] = shift;
+            bs.pass_bits[k] = w;
+            shift += w;
+        }
     }
 }
 
-__device__ void ph_scan_b(const Ctx& C, uint32_t tile, char* smem) {
+__device__ __forceinline__ void ph_scan_b(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
     const uint64_t per_frame = (uint64_t)(P.G * P.G * P.G);
-    const uint64_t total = (uint64_t)H.n_frames * per_frame;
+    const uint64_t total = H.n_counts;
     uint64_t* s_w = reinterpret_cast<uint64_t*>(smem);
     constexpr int kPer = kScanTile / kBlock;       // 16 consecutive cells per thread
     const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)threadIdx.x * kPer;
@@ -571,28 +751,24 @@ __device__ void ph_scan_b(const Ctx& C, uint32_t tile, char* smem) {
     }
 }
 
-// ---------------------------------------------------------------- phase: keys + compaction
+// ---------------------------------------------------------------- phase: keys
+// Sec. II.5(1)e: every gated point gets its cell's dense index (order-preserving image of the
+// canonical key); points are compacted in pixel order at the tile's precomputed offset.
 
-__device__ void ph_keys(const Ctx& C, uint32_t tile, char* smem) {
+__device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
     BatchState* bs = C.bs;
-    const int ci = cam_of_tile(C, tile);
-    const DevCam& cm = C.cams[ci];
+    const DevCam& cm = C.cams[cam_of_tile(C, tile)];
     const bool no_mf = P.flags & 1u;
     const bool no_sa = P.flags & 4u;
     const uint32_t G3 = (uint32_t)(P.G * P.G * P.G);
     const uint32_t* counts = C.counts + (uint64_t)cm.frame * G3;
     const uint64_t* fbase = C.fine_base + (uint64_t)cm.frame * G3;
     const bool key64 = bs->key64;
-    const uint32_t npass = no_sa ? 0u : bs->npass;
-    const uint32_t rb = H.radix_bits, D = 1u << rb;
-
-    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);                 // [4]
-    uint32_t* s_hist = s_w + 8;                                       // [npass][D]
-    uint32_t* s_misc = s_hist + kMaxPass * kMaxDigits;                // [4]
-    for (uint32_t i = threadIdx.x; i < npass * D; i += kBlock) s_hist[i] = 0;
-
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
+    const float* rx = C.raytab + cm.tab_off;
+    const float* ry = rx + cm.W;
     FrameGrid g;
     if (!no_sa) frame_grid(C.fs[cm.frame], P, g);
 
@@ -603,7 +779,7 @@ __device__ void ph_keys(const Ctx& C, uint32_t tile, char* smem) {
         const int k = gi * 4 + j;
         kv[k] = 0;
         if (!in || !gate_px(d, c, P.tau, no_mf)) return;
-        const Pt p = backproject(cm, (float)x, (float)y, d);
+        const Pt p = backproject_ray(cm, rx[x], ry[y], d);
         if (!finite3(p)) return;
         mask |= 1u << k;
         if (no_sa) return;
@@ -614,8 +790,7 @@ __device__ void ph_keys(const Ctx& C, uint32_t tile, char* smem) {
         kv[k] = fbase[cc.lin] +
                 ((((uint64_t)loc[2] << L) | (uint64_t)loc[1]) << L | (uint64_t)loc[0]);
     });
-    __syncthreads();   // s_hist zeroed
-    // per group of 4: exclusive ranks in pixel order (group-major, then thread, then j)
+    // ranks in pixel order: group-major, then thread, then j
     uint32_t off[4], tile_total = 0;
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
@@ -624,19 +799,7 @@ __device__ void ph_keys(const Ctx& C, uint32_t tile, char* smem) {
         off[gi] = tile_total + block_excl(c, s_w, tot);
         tile_total += tot;
     }
-    // look-back for the tile's base position
-    const uint32_t tag = lb_tag(*C.epoch, 0);
-    if (threadIdx.x < kWave) {
-        if (threadIdx.x == 0) st_relaxed(&C.lb_tile[tile], lb_word(tag, 1, tile_total));
-        const uint32_t pre = lookback_wave(C.lb_tile, tile, tag, bs, H.wait_ticks);
-        if (threadIdx.x == 0) {
-            st_relaxed(&C.lb_tile[tile], lb_word(tag, 2, pre + tile_total));
-            s_misc[0] = pre;
-            if (tile == H.n_px_tiles - 1) bs->M_tot = pre + tile_total;
-        }
-    }
-    __syncthreads();
-    const uint32_t pre = s_misc[0];
+    const uint32_t pre = C.tile_off[tile];
     const uint32_t pbase = cm.pix_off + (tile - cm.tile_off) * (uint32_t)kPxTile;
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
@@ -650,31 +813,111 @@ __device__ void ph_keys(const Ctx& C, uint32_t tile, char* smem) {
             if (key64) reinterpret_cast<uint64_t*>(C.keysA)[o] = kv[k];
             else reinterpret_cast<uint32_t*>(C.keysA)[o] = (uint32_t)kv[k];
             C.valsA[o] = pid;
-            for (uint32_t ps = 0; ps < npass; ++ps)
-                atomicAdd(&s_hist[ps * D + ((kv[k] >> (ps * rb)) & (D - 1))], 1u);
             ++o;
         }
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < npass * D; i += kBlock) {
-        const uint32_t v = s_hist[i];
-        if (v) atomicAdd(&bs->digit_hist[i / D][i % D], v);
-    }
 }
 
-// ---------------------------------------------------------------- phase: one LSD radix pass
-// Onesweep-style: stable rank inside the tile by wave-level digit matching, per-digit
-// decoupled look-back across tiles, LDS staging so that writes go out in digit runs.
+// ---------------------------------------------------------------- LSD radix sort
+// Reduce-then-scan per pass: tile digit histograms (UP), a scan of each digit's row over
+// the tiles (SCAN), and a stable scatter (DOWN) that ranks keys inside the tile by
+// wave-level digit matching and stages them in LDS so writes leave in digit runs.
+
+__device__ __forceinline__ uint32_t n_keys(const Ctx& C) { return min(C.bs->M_tot, C.P_cap); }
+
+template <int ITEMS>
+__device__ __forceinline__ uint32_t n_sort_tiles_real(const Ctx& C) {
+    return (n_keys(C) + kBlock * ITEMS - 1) / (kBlock * ITEMS);
+}
+
+__device__ __forceinline__ uint64_t load_key(const Ctx& C, bool from_b, bool key64, uint32_t i) {
+    const void* k = from_b ? C.keysB : C.keysA;
+    return key64 ? reinterpret_cast<const uint64_t*>(k)[i]
+                 : (uint64_t)reinterpret_cast<const uint32_t*>(k)[i];
+}
+
+// In-place exclusive scan of an LDS array of D <= kMaxDigits entries; returns the total.
+__device__ __forceinline__ uint32_t lds_excl_scan(uint32_t* a, uint32_t D, uint32_t* s_w) {
+    const uint32_t per = (D + kBlock - 1) / kBlock;
+    const uint32_t b = threadIdx.x * per;
+    uint32_t loc = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b + j < D) loc += a[b + j];
+    uint32_t tot;
+    uint32_t run = block_excl(loc, s_w, tot);
+    for (uint32_t j = 0; j < per; ++j) {
+        if (b + j < D) {
+            const uint32_t v = a[b + j];
+            a[b + j] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    return tot;
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void ph_radix_up(const Ctx& C, uint32_t pass, uint32_t tile, char* smem) {
+    constexpr int KT = kBlock * ITEMS;
+    BatchState* bs = C.bs;
+    if ((C.hdr->prm.flags & 4u) || pass >= bs->npass) return;
+    const uint32_t n = n_keys(C), nt = n_sort_tiles_real<ITEMS>(C);
+    if (tile >= nt) return;
+    const uint32_t bits = bs->pass_bits[pass], shift = bs->pass_shift[pass], D = 1u << bits;
+    const bool key64 = bs->key64, from_b = pass & 1;
+    uint32_t* s_h = reinterpret_cast<uint32_t*>(smem);
+    for (uint32_t d = threadIdx.x; d < D; d += kBlock) s_h[d] = 0;
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t idx = tile * KT + (uint32_t)i * kBlock + threadIdx.x;
+        const bool in = idx < n;
+        const uint32_t dg = in ? (uint32_t)(load_key(C, from_b, key64, idx) >> shift) & (D - 1) : 0u;
+        const uint64_t peers = match_peers(dg, in, bits);
+        const uint64_t lt = (lane_id() == 0) ? 0ull : ((~0ull) >> (64 - lane_id()));
+        if (in && (peers & lt) == 0) atomicAdd(&s_h[dg], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < D; d += kBlock) C.digit_hist[(uint64_t)d * nt + tile] = s_h[d];
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void ph_radix_scan(const Ctx& C, uint32_t pass, uint32_t d, char* smem) {
+    BatchState* bs = C.bs;
+    if ((C.hdr->prm.flags & 4u) || pass >= bs->npass) return;
+    const uint32_t D = 1u << bs->pass_bits[pass];
+    if (d >= D) return;
+    const uint32_t nt = n_sort_tiles_real<ITEMS>(C);
+    uint32_t* row = C.digit_hist + (uint64_t)d * nt;
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < nt; b += kBlock * 4) {
+        uint32_t v[4], loc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = b + threadIdx.x * 4 + j;
+            v[j] = i < nt ? row[i] : 0u;
+            loc += v[j];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_excl(loc, s_w, tot);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = b + threadIdx.x * 4 + j;
+            if (i < nt) row[i] = run;
+            run += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) C.digit_total[d] = carry;
+}
 
 template <typename K, int ITEMS>
-__device__ void radix_pass(const Ctx& C, uint32_t pass, uint32_t tile, char* smem) {
+__device__ void radix_down(const Ctx& C, uint32_t pass, uint32_t tile, char* smem) {
     constexpr int KT = kBlock * ITEMS;
-    const CallHdr& H = *C.hdr;
     BatchState* bs = C.bs;
-    const uint32_t n = min(bs->M_tot, C.P_cap);
-    const uint32_t rb = H.radix_bits, D = 1u << rb;
-    const uint32_t shift = pass * rb;
-    if ((uint64_t)tile * KT >= n) return;
+    const uint32_t n = n_keys(C), nt = n_sort_tiles_real<ITEMS>(C);
+    const uint32_t bits = bs->pass_bits[pass], shift = bs->pass_shift[pass], D = 1u << bits;
     const K* kin = reinterpret_cast<const K*>((pass & 1) ? C.keysB : C.keysA);
     const uint32_t* vin = (pass & 1) ? C.valsB : C.valsA;
     K* kout = reinterpret_cast<K*>((pass & 1) ? C.keysA : C.keysB);
@@ -686,97 +929,95 @@ __device__ void radix_pass(const Ctx& C, uint32_t pass, uint32_t tile, char* sme
     uint32_t* s_doff = s_wc + 4 * kMaxDigits;                           // [D] tile digit offsets
     uint32_t* s_gb = s_doff + kMaxDigits;                               // [D] global base
     uint32_t* s_w = s_gb + kMaxDigits;                                  // [8]
+    uint32_t* s_cam = s_w + 8;                                          // [n_cams] pix_off
     const uint32_t tid = threadIdx.x, w = tid / kWave, l = lane_id();
-    for (uint32_t i = tid; i < 4 * D; i += kBlock) s_wc[i] = 0;
-    __syncthreads();
-
-    // load (wave-striped: wave w owns a contiguous run of ITEMS*64 keys)
-    const uint64_t t0 = (uint64_t)tile * KT + (uint64_t)w * (ITEMS * kWave);
+    const uint32_t nc = C.hdr->n_cams;
+    const bool last = pass + 1 == bs->npass && !(C.hdr->prm.flags & 1u);
+    // issue this tile's key and id loads first: their latency overlaps the scans below
+    const uint32_t t0 = tile * KT + w * (ITEMS * kWave);
     K key[ITEMS];
     uint32_t val[ITEMS], rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint64_t idx = t0 + (uint64_t)i * kWave + l;
+        const uint32_t idx = t0 + (uint32_t)i * kWave + l;
         const bool in = idx < n;
         key[i] = in ? kin[idx] : (K)0;
         val[i] = in ? vin[idx] : 0u;
     }
+    if (last)
+        for (uint32_t i = tid; i < nc; i += kBlock) s_cam[i] = C.camlite[i].pix_off;
+    for (uint32_t i = tid; i < 4 * D; i += kBlock) s_wc[i] = 0;
+    // digit starts: exclusive scan of the digit totals
+    for (uint32_t d = tid; d < D; d += kBlock) s_gb[d] = C.digit_total[d];
+    __syncthreads();
+    (void)lds_excl_scan(s_gb, D, s_w);
+    // add the digit's offset of this tile (its row was scanned over the tiles)
+    for (uint32_t d = tid; d < D; d += kBlock) s_gb[d] += C.digit_hist[(uint64_t)d * nt + tile];
+
     const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
     uint32_t* wc = s_wc + w * D;
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint64_t idx = t0 + (uint64_t)i * kWave + l;
+        const uint32_t idx = t0 + (uint32_t)i * kWave + l;
         const bool in = idx < n;
         const uint32_t dg = (uint32_t)(key[i] >> shift) & (D - 1);
-        uint64_t peers = __ballot(in);
-        for (uint32_t b = 0; b < rb; ++b) {
-            const uint64_t bal = __ballot((dg >> b) & 1u);
-            peers &= ((dg >> b) & 1u) ? bal : ~bal;
-        }
+        const uint64_t peers = match_peers(dg, in, bits);
         const uint32_t before = wc[dg];
         const uint32_t lower = (uint32_t)__popcll(peers & lt);
         rank[i] = before + lower;
-        // the lowest lane of each peer group bumps the counter after everyone has read it
         __builtin_amdgcn_wave_barrier();
         if (in && lower == 0) wc[dg] = before + (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per-digit tile totals and per-wave offsets
-    uint32_t dtot = 0;
-    if (tid < D) {
+    // per-digit tile totals (into s_doff) and per-wave offsets inside each digit
+    for (uint32_t d = tid; d < D; d += kBlock) {
         uint32_t acc = 0;
         for (int ww = 0; ww < 4; ++ww) {
-            const uint32_t c = s_wc[ww * D + tid];
-            s_wc[ww * D + tid] = acc;
+            const uint32_t c = s_wc[ww * D + d];
+            s_wc[ww * D + d] = acc;
             acc += c;
         }
-        dtot = acc;
+        s_doff[d] = acc;
     }
-    const uint32_t tag = lb_tag(*C.epoch, 2 + pass);
-    uint64_t* lb = C.lb_digit;
-    if (tid < D) st_relaxed(&lb[(uint64_t)tile * D + tid], lb_word(tag, 1, dtot));
-    uint32_t tot_unused;
-    const uint32_t doff = block_excl(tid < D ? dtot : 0u, s_w, tot_unused);
-    if (tid < D) s_doff[tid] = doff;
     __syncthreads();
-    // scatter into LDS in (digit, original order)
+    (void)lds_excl_scan(s_doff, D, s_w);
+    for (uint32_t d = tid; d < D; d += kBlock) s_gb[d] -= s_doff[d];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint64_t idx = t0 + (uint64_t)i * kWave + l;
+        const uint32_t idx = t0 + (uint32_t)i * kWave + l;
         if (idx >= n) continue;
         const uint32_t dg = (uint32_t)(key[i] >> shift) & (D - 1);
         const uint32_t pos = s_doff[dg] + s_wc[w * D + dg] + rank[i];
         s_key[pos] = key[i];
         s_val[pos] = val[i];
     }
-    // global base of each digit: digit start + prefix of earlier tiles
-    const uint32_t dstart = block_excl(tid < D ? bs->digit_hist[pass][tid] : 0u, s_w, tot_unused);
-    if (tid < D) {
-        const uint32_t pre = lookback_thread(lb, tile, D, tid, tag, bs, H.wait_ticks);
-        st_relaxed(&lb[(uint64_t)tile * D + tid], lb_word(tag, 2, pre + dtot));
-        s_gb[tid] = dstart + pre - s_doff[tid];
-    }
     __syncthreads();
-    const uint32_t cnt = (uint32_t)((n - (uint64_t)tile * KT) < (uint64_t)KT
-                                        ? (n - (uint64_t)tile * KT) : (uint64_t)KT);
+    const uint32_t cnt = min((uint32_t)KT, n - tile * KT);
     for (uint32_t s = tid; s < cnt; s += kBlock) {
         const K kk = s_key[s];
         const uint32_t dg = (uint32_t)(kk >> shift) & (D - 1);
         const uint32_t dst = s_gb[dg] + s;
         if (dst >= n) { raise_error(bs, kErrBounds); continue; }
+        const uint32_t v = s_val[s];
         kout[dst] = kk;
-        vout[dst] = s_val[s];
+        vout[dst] = v;
+        if (last) {
+            // the per-cell phase ranks members by confidence: hand it over in sorted order
+            const CamLite& cl = C.camlite[last_le(s_cam, (int)nc, v)];
+            C.conf_sorted[dst] = __float_as_uint(glob(cl.conf)[v - cl.pix_off]);
+        }
     }
 }
 
 template <int ITEMS>
-__device__ void ph_radix(const Ctx& C, uint32_t pass, uint32_t tile, char* smem) {
+__device__ __forceinline__ void ph_radix_down(const Ctx& C, uint32_t pass, uint32_t tile, char* smem) {
     BatchState* bs = C.bs;
-    if (C.hdr->prm.flags & 4u) return;
-    if (pass >= bs->npass) return;
-    if (bs->key64) radix_pass<uint64_t, ITEMS>(C, pass, tile, smem);
-    else radix_pass<uint32_t, ITEMS>(C, pass, tile, smem);
+    if ((C.hdr->prm.flags & 4u) || pass >= bs->npass) return;
+    if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
+    if (bs->key64) radix_down<uint64_t, ITEMS>(C, pass, tile, smem);
+    else radix_down<uint32_t, ITEMS>(C, pass, tile, smem);
 }
 
 // final (sorted) buffers
@@ -784,98 +1025,98 @@ __device__ __forceinline__ const uint32_t* sorted_vals(const Ctx& C) {
     return (C.bs->npass & 1) ? C.valsB : C.valsA;
 }
 __device__ __forceinline__ uint64_t sorted_key(const Ctx& C, uint32_t i) {
-    const bool b = C.bs->npass & 1;
-    if (C.bs->key64) return reinterpret_cast<const uint64_t*>(b ? C.keysB : C.keysA)[i];
-    return reinterpret_cast<const uint32_t*>(b ? C.keysB : C.keysA)[i];
+    return load_key(C, C.bs->npass & 1, C.bs->key64, i);
 }
 
-// frame index of a batch pixel id (frames staged in LDS by pix_begin)
-__device__ __forceinline__ int frame_of_pix(const uint32_t* s_fpix, int nf, uint32_t id) {
-    int lo = 0, hi = nf - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_fpix[mid] <= id) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// ---------------------------------------------------------------- phase: cell heads
+// ---------------------------------------------------------------- cell heads
+// Cells are runs of equal keys in sorted order: count the run heads per tile, scan, write
+// each cell's first position, and record where each frame's cells begin.
 
 template <int ITEMS>
-__device__ void ph_heads(const Ctx& C, uint32_t tile, char* smem) {
-    constexpr int KT = kBlock * ITEMS;
-    const CallHdr& H = *C.hdr;
-    BatchState* bs = C.bs;
-    if (H.prm.flags & 4u) return;
-    const uint32_t n = min(bs->M_tot, C.P_cap);
-    const uint32_t tag = lb_tag(*C.epoch, 1);
-    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);        // [8]
-    uint32_t* s_fpix = s_w + 8;                               // [F]
-    uint32_t* s_fcnt = s_fpix + 64;                           // [F]
-    const uint32_t nf = H.n_frames;
-    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
-        s_fpix[f] = C.frames[f].pix_begin;
-        s_fcnt[f] = 0;
-    }
-    __syncthreads();
-    const uint64_t t0 = (uint64_t)tile * KT + (uint64_t)threadIdx.x * ITEMS;
-    const bool active = (uint64_t)tile * KT < n;
-    // thread-contiguous items so that the compaction keeps order
-    uint32_t hmask = 0, c = 0;
-    uint64_t prev = 0;
-    if (active) {
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint64_t idx = t0 + i;
-            if (idx >= n) break;
-            const uint64_t k = sorted_key(C, (uint32_t)idx);
-            if (i == 0) prev = idx ? sorted_key(C, (uint32_t)idx - 1) : ~k;
-            if (idx == 0 || k != prev) { hmask |= 1u << i; ++c; }
-            prev = k;
-        }
-    }
-    uint32_t tot;
-    const uint32_t ex = block_excl(c, s_w, tot);
-    __shared__ uint32_t s_pre;
-    if (threadIdx.x < kWave) {
-        if (active) {
-            if (threadIdx.x == 0) st_relaxed(&C.lb_tile[tile], lb_word(tag, 1, tot));
-            const uint32_t pre = lookback_wave(C.lb_tile, tile, tag, bs, H.wait_ticks);
-            if (threadIdx.x == 0) {
-                st_relaxed(&C.lb_tile[tile], lb_word(tag, 2, pre + tot));
-                s_pre = pre;
-                if ((uint64_t)(tile + 1) * KT >= n) {   // last real tile
-                    bs->S_tot = pre + tot;
-                    if (pre + tot <= C.P_cap) C.cell_start[pre + tot] = n;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    uint32_t o = s_pre + ex;
-    const uint32_t* vals = sorted_vals(C);
+__device__ __forceinline__ uint32_t head_mask(const Ctx& C, uint32_t tile, uint32_t n) {
+    const uint32_t t0 = tile * (kBlock * ITEMS) + threadIdx.x * ITEMS;
+    uint32_t m = 0;
+    if (t0 >= n) return 0;
+    uint64_t prev = t0 ? sorted_key(C, t0 - 1) : 0;
     for (int i = 0; i < ITEMS; ++i) {
-        if (!(hmask >> i & 1u)) continue;
-        const uint32_t idx = (uint32_t)(t0 + i);
-        if (o < C.P_cap) C.cell_start[o] = idx; else raise_error(bs, kErrBounds);
-        ++o;
-        const int f = frame_of_pix(s_fpix, (int)nf, vals[idx]);
-        atomicAdd(&s_fcnt[f], 1u);
+        const uint32_t idx = t0 + i;
+        if (idx >= n) break;
+        const uint64_t k = sorted_key(C, idx);
+        if (idx == 0 || k != prev) m |= 1u << i;
+        prev = k;
     }
-    __syncthreads();
-    for (uint32_t f = threadIdx.x; f < nf; f += kBlock)
-        if (s_fcnt[f]) atomicAdd(&C.fs[f].S, s_fcnt[f]);
+    return m;
 }
 
-// ---------------------------------------------------------------- phase: cells
-// One thread per cell: top-3 representatives (Sec. II.5(2)a), local views and
-// consistency (II.5(2)b, Eq. 4-7), joint weight and fusion (Eq. 10-11), output.
+template <int ITEMS>
+__device__ __forceinline__ void ph_head_count(const Ctx& C, uint32_t tile, char* smem) {
+    if (C.hdr->prm.flags & 4u) return;
+    const uint32_t n = n_keys(C);
+    if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
+    const uint32_t c = __popc(head_mask<ITEMS>(C, tile, n));
+    const uint32_t tot = block_sum(c, reinterpret_cast<uint32_t*>(smem));
+    if (threadIdx.x == 0) C.head_cnt[tile] = tot;
+}
 
+template <int ITEMS>
+__device__ __forceinline__ void ph_head_scan(const Ctx& C, uint32_t, char* smem) {
+    if (C.hdr->prm.flags & 4u) return;
+    const uint32_t n = n_keys(C), nt = n_sort_tiles_real<ITEMS>(C);
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < nt; b += kBlock) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < nt ? C.head_cnt[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl(v, s_w, tot);
+        if (i < nt) C.head_cnt[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        C.bs->S_tot = carry;
+        if (carry <= C.P_cap) C.cell_start[carry] = n;
+    }
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void ph_head_write(const Ctx& C, uint32_t tile, char* smem) {
+    const CallHdr& H = *C.hdr;
+    if (H.prm.flags & 4u) return;
+    const uint32_t n = n_keys(C);
+    if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);        // [8]
+    uint32_t* s_fpix = s_w + 8;                               // [F]
+    const uint32_t nf = H.n_frames;
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) s_fpix[f] = C.frames[f].pix_begin;
+    const uint32_t m = head_mask<ITEMS>(C, tile, n);
+    uint32_t tot;
+    uint32_t o = C.head_cnt[tile] + block_excl(__popc(m), s_w, tot);   // syncs s_fpix too
+    const uint32_t t0 = tile * (kBlock * ITEMS) + threadIdx.x * ITEMS;
+    const uint32_t* vals = sorted_vals(C);
+    for (int i = 0; i < ITEMS; ++i) {
+        if (!(m >> i & 1u)) continue;
+        const uint32_t idx = t0 + i;
+        if (o < C.P_cap) C.cell_start[o] = idx; else raise_error(C.bs, kErrBounds);
+        // the first cell of a frame: its first element follows another frame's element
+        const int f = last_le(s_fpix, (int)nf, vals[idx]);
+        if (idx == 0 || last_le(s_fpix, (int)nf, vals[idx - 1]) != f) {
+            C.fs[f].cell_begin = o;
+            C.fs[f].has_cells = 1;
+        }
+        ++o;
+    }
+}
+
+// ---------------------------------------------------------------- cell helpers
+
+// A member of a cell, ranked by confidence first; its pixel id and position are fetched
+// only when needed (a tie in confidence, or once it is a representative).
 struct Cand {
     float C;
-    uint32_t id;     // batch pixel id
-    int cam;
-    bool hasp;
+    uint32_t k;      // sorted position
+    uint32_t id;     // batch pixel id (valid when st >= 1)
+    int cam;         // camera (valid when st >= 1)
+    int st;          // 0: C only, 1: + id and camera, 2: + position
     Pt p;
 };
 
@@ -884,42 +1125,74 @@ struct CellsShared {
     uint32_t fpix[kMaxFrames];                  // frame pix_begin
     uint32_t key_begin[kMaxFrames];             // frame's first sorted/compacted position
     uint32_t cell_begin[kMaxFrames];            // frame's first global cell
+    uint32_t w[8];
 };
 
-__device__ __forceinline__ void ensure_p(const Ctx& C, Cand& a) {
-    if (a.hasp) return;
-    const DevCam& cm = C.cams[a.cam];
+struct CellCtx {
+    const Ctx& C;
+    const CamLite* cams;      // LDS copy when the batch has few cameras, else global
+    const uint32_t* cam_pix;  // LDS
+    const uint32_t* vals;
+    int nc;
+};
+
+__device__ __forceinline__ void ensure_id(const CellCtx& X, Cand& a) {
+    if (a.st >= 1) return;
+    a.id = glob(X.vals)[a.k];
+    a.cam = last_le(X.cam_pix, X.nc, a.id);
+    a.st = 1;
+}
+
+// (x, y) of pixel `loc` of a camera: a float estimate of loc / W, then exact correction
+template <typename Cam>
+__device__ __forceinline__ void pixel_xy(const Cam& cm, uint32_t loc, uint32_t& x, uint32_t& y) {
+    const int64_t W = cm.W;
+    int64_t yy = (int64_t)((float)loc * cm.invW);
+    int64_t r = (int64_t)loc - yy * W;
+    while (r < 0) { --yy; r += W; }
+    while (r >= W) { ++yy; r -= W; }
+    y = (uint32_t)yy;
+    x = (uint32_t)r;
+}
+
+__device__ __forceinline__ void ensure_p(const CellCtx& X, Cand& a) {
+    if (a.st >= 2) return;
+    ensure_id(X, a);
+    const CamLite& cm = X.cams[a.cam];
     const uint32_t loc = a.id - cm.pix_off;
-    const uint32_t y = loc / (uint32_t)cm.W, x = loc - y * (uint32_t)cm.W;
-    a.p = backproject(cm, (float)x, (float)y, cm.depth[loc]);
-    a.hasp = true;
+    uint32_t x, y;
+    pixel_xy(cm, loc, x, y);
+    a.p = backproject_ray(cm, glob(cm.rx)[x], glob(cm.ry)[y], glob(cm.depth)[loc]);
+    a.st = 2;
 }
 
 // strict "a ranks before b": C descending, then x, y, z ascending, then pixel id
-__device__ __forceinline__ bool rank_before(const Ctx& C, Cand& a, Cand& b) {
+__device__ __forceinline__ bool rank_before(const CellCtx& X, Cand& a, Cand& b) {
     if (a.C != b.C) return a.C > b.C;
-    ensure_p(C, a);
-    ensure_p(C, b);
+    ensure_p(X, a);
+    ensure_p(X, b);
     if (a.p.x != b.p.x) return a.p.x < b.p.x;
     if (a.p.y != b.p.y) return a.p.y < b.p.y;
     if (a.p.z != b.p.z) return a.p.z < b.p.z;
     return a.id < b.id;
 }
 
-// -ln V of representative (cam ri, point p): Eq. 4-7 over the first K-1 views by distance
-__device__ double neg_log_v(const Ctx& C, int ri, const Pt& p, uint32_t fcam0, uint32_t fcams,
-                            const DevParams& P) {
+// -ln V of representative (cam ri, point p): Eq. 4-7 over the first K-1 views by distance.
+// KV >= K - 1 is the compile-time size of the candidate list.
+template <int KV>
+__device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const Pt& p,
+                                            uint32_t fcam0, uint32_t fcams, const DevParams& P) {
     const int keep = (P.K < (int)fcams ? P.K : (int)fcams) - 1;
     if (keep <= 0) return 0.0;
-    float bd[kMaxK - 1];
-    uint32_t br[kMaxK - 1];
-    int bj[kMaxK - 1], bx[kMaxK - 1], by[kMaxK - 1];
+    float bd[KV];
+    uint32_t br[KV];
+    int bj[KV];
     int nb = 0;
     for (uint32_t j = fcam0; j < fcam0 + fcams; ++j) {
         if ((int)j == ri) continue;
-        const DevCam& cj = C.cams[j];
-        int px, py;
-        if (!project(cj, p, px, py)) continue;
+        const CamLite& cj = cams[j];
+        float X, Y, Z;
+        if (!in_view_fast(cj, p, X, Y, Z)) continue;
         const float dx = p.x - cj.c[0], dy = p.y - cj.c[1], dz = p.z - cj.c[2];
         const float d2 = (dx * dx + dy * dy) + dz * dz;
         // insertion into the sorted list of the best `keep` candidates: carry the
@@ -927,28 +1200,43 @@ __device__ double neg_log_v(const Ctx& C, int ri, const Pt& p, uint32_t fcam0, u
         // nb are free, so whatever is carried into them is discarded)
         float cd = d2;
         uint32_t cr = cj.rank;
-        int cjx = (int)j, cx = px, cy = py;
+        int cjx = (int)j;
 #pragma unroll
-        for (int q = 0; q < kMaxK - 1; ++q) {
+        for (int q = 0; q < KV; ++q) {
             if (q < keep && (q >= nb || cd < bd[q] || (cd == bd[q] && cr < br[q]))) {
-                const float td = bd[q]; bd[q] = cd; cd = td;
+                const float t = bd[q]; bd[q] = cd; cd = t;
                 const uint32_t tr = br[q]; br[q] = cr; cr = tr;
                 const int tj = bj[q]; bj[q] = cjx; cjx = tj;
-                const int tx = bx[q]; bx[q] = cx; cx = tx;
-                const int ty = by[q]; by[q] = cy; cy = ty;
             }
         }
         if (nb < keep) ++nb;
     }
+    // exact pixels of the kept views (the camera-frame point is recomputed: it is cheaper
+    // than carrying it through the list), then their depths as independent gathers
+    int bx[KV], by[KV];
+    float dv[KV];
+#pragma unroll
+    for (int q = 0; q < KV; ++q) {
+        dv[q] = 0.0f;
+        bx[q] = by[q] = 0;
+        if (q < nb) {
+            const CamLite& cj = cams[bj[q]];
+            const float X = ((cj.R[0] * p.x + cj.R[1] * p.y) + cj.R[2] * p.z) + cj.t[0];
+            const float Y = ((cj.R[3] * p.x + cj.R[4] * p.y) + cj.R[5] * p.z) + cj.t[1];
+            const float Z = ((cj.R[6] * p.x + cj.R[7] * p.y) + cj.R[8] * p.z) + cj.t[2];
+            exact_pixel(cj, X, Y, Z, bx[q], by[q]);
+            dv[q] = glob(cj.depth)[(uint32_t)by[q] * (uint32_t)cj.W + (uint32_t)bx[q]];
+        }
+    }
     double s = 0.0;
     int m = 0;
 #pragma unroll
-    for (int q = 0; q < kMaxK - 1; ++q) {
+    for (int q = 0; q < KV; ++q) {
         if (q >= nb) continue;
-        const DevCam& cj = C.cams[bj[q]];
-        const float d = cj.depth[(uint32_t)by[q] * (uint32_t)cj.W + (uint32_t)bx[q]];
+        const float d = dv[q];
         if (!(__builtin_isfinite(d) && d > 0.0f)) continue;
-        const Pt Q = backproject(cj, (float)bx[q], (float)by[q], d);
+        const CamLite& cj = cams[bj[q]];
+        const Pt Q = backproject_ray(cj, glob(cj.rx)[bx[q]], glob(cj.ry)[by[q]], d);
         const double ex = (double)p.x - (double)Q.x;
         const double ey = (double)p.y - (double)Q.y;
         const double ez = (double)p.z - (double)Q.z;
@@ -960,130 +1248,183 @@ __device__ double neg_log_v(const Ctx& C, int ri, const Pt& p, uint32_t fcam0, u
     return s / ((double)m * (sig * sig));
 }
 
-__device__ void emit_cell(const Ctx& C, const DevFrame& fr, uint32_t o, Cand* rep, int nrep,
-                          const double* expo, uint32_t nmem, uint64_t key) {
-    double a[3] = {0.0, 0.0, 0.0}, amax = -INFINITY;
+__device__ __forceinline__ void emit_cell(const CamLite* cams, const DevFrame& fr, uint32_t o, Cand* rep,
+                          int nrep, const double* expo, uint32_t nmem, uint64_t key) {
+    // joint weights w = C V (Eq. 10) and the normalised weighted mean (Eq. 11); when every
+    // weight underflows the same mean is taken in the log domain (softmax of ln C - ln V^-1)
+    double wv[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        if (r >= nrep) continue;
-        a[r] = log((double)rep[r].C) - expo[r];
-        amax = a[r] > amax ? a[r] : amax;
+        if (r < nrep) wv[r] = (double)rep[r].C * exp(-expo[r]);
+        wsum += wv[r];
     }
-    double ex[3] = {0.0, 0.0, 0.0};
-    double se = 0.0;
+    double pis[3] = {0.0, 0.0, 0.0};
+    if (wsum > 1e-280) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        if (r < nrep) ex[r] = exp(a[r] - amax);
-        se += ex[r];
+        for (int r = 0; r < 3; ++r) pis[r] = wv[r] / wsum;
+    } else {
+        double a[3] = {0.0, 0.0, 0.0}, amax = -INFINITY, se = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            if (r >= nrep) continue;
+            a[r] = log((double)rep[r].C) - expo[r];
+            amax = a[r] > amax ? a[r] : amax;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            pis[r] = r < nrep ? exp(a[r] - amax) : 0.0;
+            se += pis[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) pis[r] /= se;
     }
-    double x = 0.0, y = 0.0, z = 0.0, wsum = 0.0;
+    double x = 0.0, y = 0.0, z = 0.0;
     double cr = 0.0, cg = 0.0, cb = 0.0;
     const bool rgb = fr.rgb != nullptr && fr.has_rgb;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        const double pi = ex[r] / se;
+        const double pi = pis[r];
         if (r < nrep) {
             x += pi * (double)rep[r].p.x;
             y += pi * (double)rep[r].p.y;
             z += pi * (double)rep[r].p.z;
-            wsum += (double)rep[r].C * exp(-expo[r]);
             if (rgb) {
-                const DevCam& cm = C.cams[rep[r].cam];
-                const uint8_t* px = cm.rgb + (uint64_t)(rep[r].id - cm.pix_off) * 3;
+                const CamLite& cm = cams[rep[r].cam];
+                const auto px = glob(cm.rgb + (uint64_t)(rep[r].id - cm.pix_off) * 3);
                 cr += pi * (double)px[0];
                 cg += pi * (double)px[1];
                 cb += pi * (double)px[2];
             }
         } else {
             x += pi * 0.0; y += pi * 0.0; z += pi * 0.0;
-            wsum += 0.0;
         }
     }
-    fr.xyz[(uint64_t)o * 3 + 0] = (float)x;
-    fr.xyz[(uint64_t)o * 3 + 1] = (float)y;
-    fr.xyz[(uint64_t)o * 3 + 2] = (float)z;
-    fr.weight[o] = (float)(wsum / (double)nrep);
+    glob(fr.xyz)[(uint64_t)o * 3 + 0] = (float)x;
+    glob(fr.xyz)[(uint64_t)o * 3 + 1] = (float)y;
+    glob(fr.xyz)[(uint64_t)o * 3 + 2] = (float)z;
+    glob(fr.weight)[o] = (float)(wsum / (double)nrep);
     if (rgb) {
         const double v[3] = {cr, cg, cb};
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
             double t = rint(v[k]);
             t = t < 0.0 ? 0.0 : (t > 255.0 ? 255.0 : t);
-            fr.rgb[(uint64_t)o * 3 + k] = (uint8_t)t;
+            glob(fr.rgb)[(uint64_t)o * 3 + k] = (uint8_t)t;
         }
     }
-    if (fr.n_members) fr.n_members[o] = nmem;
+    if (fr.n_members) glob(fr.n_members)[o] = nmem;
     if (fr.reps) {
+#pragma unroll
         for (int r = 0; r < 3; ++r)
-            fr.reps[(uint64_t)o * 3 + r] = r < nrep ? rep[r].id - fr.pix_begin : kPad;
+            glob(fr.reps)[(uint64_t)o * 3 + r] = r < nrep ? rep[r].id - fr.pix_begin : kPad;
     }
-    if (fr.keys) fr.keys[o] = key;
+    if (fr.keys) glob(fr.keys)[o] = key;
 }
 
-__device__ void ph_cells(const Ctx& C, uint32_t item, char* smem) {
+// ---------------------------------------------------------------- phase: cells
+// One thread per cell: top-3 representatives (Sec. II.5(2)a), local views and
+// consistency (II.5(2)b, Eq. 4-7), joint weight and fusion (Eq. 10-11), output.
+
+template <int KV, bool LDS_CAMS>
+__device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
     BatchState* bs = C.bs;
     CellsShared& sh = *reinterpret_cast<CellsShared*>(smem);
+    CamLite* s_cams = reinterpret_cast<CamLite*>(smem + sizeof(CellsShared));
     const uint32_t nf = H.n_frames, nc = H.n_cams;
     const bool no_sa = P.flags & 4u, no_mf = P.flags & 1u, no_dc = P.flags & 2u;
-    for (uint32_t i = threadIdx.x; i < nc; i += kBlock) sh.cam_pix[i] = C.cams[i].pix_off;
-    if (threadIdx.x == 0) {
-        uint32_t kb = 0, cb = 0;
-        for (uint32_t f = 0; f < nf; ++f) {
-            sh.fpix[f] = C.frames[f].pix_begin;
-            sh.key_begin[f] = kb;
-            sh.cell_begin[f] = cb;
-            kb += C.fs[f].M;
-            cb += no_sa ? C.fs[f].M : C.fs[f].S;
-        }
+    for (uint32_t i = threadIdx.x; i < nc; i += kBlock) {
+        sh.cam_pix[i] = C.camlite[i].pix_off;
+        if (LDS_CAMS) s_cams[i] = C.camlite[i];
+    }
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
+        sh.fpix[f] = C.frames[f].pix_begin;
+        sh.key_begin[f] = C.fs[f].key_begin;
+        sh.cell_begin[f] = no_sa ? C.fs[f].key_begin : C.fs[f].cell_begin;
     }
     __syncthreads();
-    const uint32_t M_tot = min(bs->M_tot, C.P_cap);
+    const uint32_t M_tot = n_keys(C);
     const uint32_t S = min(no_sa ? bs->M_tot : bs->S_tot, M_tot);
     const uint32_t n_items = H.n_cell_items;
     const uint32_t b0 = (uint32_t)(((uint64_t)S * item) / n_items);
     const uint32_t b1 = (uint32_t)(((uint64_t)S * (item + 1)) / n_items);
+    if (b0 >= b1) return;
     const uint32_t* vals = no_sa ? C.valsA : sorted_vals(C);
+    // one source per instantiation, so LDS reads compile to ds_read (a pointer that may be
+    // either LDS or global would make every camera read a flat access that waits for all
+    // outstanding global loads)
+    const CamLite* cams = LDS_CAMS ? s_cams : C.camlite;
+    const CellCtx X{C, cams, sh.cam_pix, vals, (int)nc};
+    // confidences in sorted order come from the last radix pass (none ran: gather them)
+    const bool have_cs = !no_sa && !no_mf && bs->npass > 0;
     const uint32_t G3 = (uint32_t)(P.G * P.G * P.G);
-    uint32_t rsum_frame = 0xFFFFFFFFu, rsum = 0;
+    // representatives are counted per frame: the item's first frame in a block reduction,
+    // any other frame directly (items rarely straddle frames)
+    const uint32_t k_first = no_sa ? b0 : min(C.cell_start[b0], M_tot - 1);
+    const int f_item = last_le(sh.fpix, (int)nf, vals[k_first]);
+    uint32_t rsum = 0;
     for (uint32_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
         uint32_t start, end;
         if (no_sa) { start = s; end = s + 1; }
-        else { start = C.cell_start[s]; end = C.cell_start[s + 1]; }
+        else { start = glob(C.cell_start)[s]; end = glob(C.cell_start)[s + 1]; }
         if (end > M_tot || start >= end) { raise_error(bs, kErrBounds); continue; }
-        const uint32_t id0 = vals[start];
-        const int f = frame_of_pix(sh.fpix, (int)nf, id0);
-        if (id0 >= H.P_tot) { raise_error(bs, kErrBounds); continue; }
-        const DevFrame& fr = C.frames[f];
         Cand rep[3];
         int nrep = 0;
-        for (uint32_t k = start; k < end; ++k) {
-            Cand c;
-            c.id = vals[k];
-            c.cam = cam_of_pix(sh.cam_pix, (int)nc, c.id);
-            const DevCam& cm = C.cams[c.cam];
-            if (c.id - cm.pix_off >= (uint32_t)cm.W * (uint32_t)cm.H) {
-                raise_error(bs, kErrBounds);
-                continue;
+        // members in chunks of 8: their confidences are loaded together (one wait per
+        // chunk instead of one per member), then ranked one by one in sorted order
+        for (uint32_t k0 = start; k0 < end; k0 += 8) {
+            float cv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t k = k0 + j;
+                cv[j] = 1.0f;
+                if (k < end && !no_mf && have_cs) cv[j] = __uint_as_float(glob(C.conf_sorted)[k]);
             }
-            c.C = no_mf ? 1.0f : cm.conf[c.id - cm.pix_off];
-            c.hasp = false;
-            if (nrep == 3 && !rank_before(C, c, rep[2])) continue;
-            if (nrep < 1 || rank_before(C, c, rep[0])) {
-                rep[2] = rep[1]; rep[1] = rep[0]; rep[0] = c;
-            } else if (nrep < 2 || rank_before(C, c, rep[1])) {
-                rep[2] = rep[1]; rep[1] = c;
-            } else {
-                rep[2] = c;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t k = k0 + j;
+                if (k >= end) break;
+                Cand c;
+                c.k = k;
+                c.st = 0;
+                c.C = cv[j];
+                if (!no_mf && !have_cs) {
+                    ensure_id(X, c);
+                    const CamLite& cm = cams[c.cam];
+                    c.C = glob(cm.conf)[c.id - cm.pix_off];
+                }
+                if (nrep == 3 && !rank_before(X, c, rep[2])) continue;
+                if (nrep < 1 || rank_before(X, c, rep[0])) {
+                    rep[2] = rep[1]; rep[1] = rep[0]; rep[0] = c;
+                } else if (nrep < 2 || rank_before(X, c, rep[1])) {
+                    rep[2] = rep[1]; rep[1] = c;
+                } else {
+                    rep[2] = c;
+                }
+                if (nrep < 3) ++nrep;
             }
-            if (nrep < 3) ++nrep;
         }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            if (r < nrep) ensure_id(X, rep[r]);
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            if (r >= nrep) continue;
+            const CamLite& cm = cams[rep[r].cam];
+            if (rep[r].id >= H.P_tot || rep[r].id - cm.pix_off >= (uint32_t)cm.W * (uint32_t)cm.H)
+                bad = true;
+        }
+        if (bad || nrep == 0) { raise_error(bs, kErrBounds); continue; }
+        const int f = last_le(sh.fpix, (int)nf, rep[0].id);
+        const DevFrame& fr = C.frames[f];
         double expo[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             if (r >= nrep) continue;
-            ensure_p(C, rep[r]);
-            if (!no_dc) expo[r] = neg_log_v(C, rep[r].cam, rep[r].p, fr.cam_begin, fr.n_cams, P);
+            ensure_p(X, rep[r]);
+            if (!no_dc) expo[r] = neg_log_v<KV>(cams, rep[r].cam, rep[r].p, fr.cam_begin, fr.n_cams, P);
         }
         uint64_t key;
         if (no_sa) {
@@ -1099,35 +1440,42 @@ __device__ void ph_cells(const Ctx& C, uint32_t item, char* smem) {
         }
         const uint32_t o = s - sh.cell_begin[f];
         if (o < fr.capacity) {
-            emit_cell(C, fr, o, rep, nrep, expo, end - start, key);
-            if (fr.moff) fr.moff[o] = start - sh.key_begin[f];
+            emit_cell(cams, fr, o, rep, nrep, expo, end - start, key);
+            if (fr.moff) glob(fr.moff)[o] = start - sh.key_begin[f];
         }
         if (fr.mids) {
             for (uint32_t k = start; k < end; ++k) {
                 const uint32_t mo = k - sh.key_begin[f];
-                if (mo < fr.member_capacity) fr.mids[mo] = vals[k] - fr.pix_begin;
+                if (mo < fr.member_capacity) glob(fr.mids)[mo] = glob(vals)[k] - fr.pix_begin;
             }
         }
-        // representatives per frame (aggregated per thread run, flushed on frame change)
-        if ((uint32_t)f != rsum_frame) {
-            if (rsum) atomicAdd(&C.fs[rsum_frame].R, rsum);
-            rsum_frame = (uint32_t)f;
-            rsum = 0;
-        }
-        rsum += (uint32_t)nrep;
+        if (f == f_item) rsum += (uint32_t)nrep;
+        else atomicAdd(&C.fs[f].R[item % kRSlots], (uint32_t)nrep);
     }
-    if (rsum) atomicAdd(&C.fs[rsum_frame].R, rsum);
+    const uint32_t tot = block_sum(rsum, sh.w);
+    if (threadIdx.x == 0 && tot) atomicAdd(&C.fs[f_item].R[item % kRSlots], tot);
 }
 
 // ---------------------------------------------------------------- phase: final counts
 
-__device__ void ph_final(const Ctx& C, uint32_t, char*) {
+__device__ __forceinline__ void ph_final(const Ctx& C, uint32_t, char*) {
     const CallHdr& H = *C.hdr;
     const bool no_sa = H.prm.flags & 4u;
-    for (uint32_t f = threadIdx.x; f < H.n_frames; f += kBlock) {
+    const uint32_t nf = H.n_frames;
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
         const DevFrame& fr = C.frames[f];
         const FrameState& st = C.fs[f];
-        const uint32_t S = no_sa ? st.M : st.S;
+        uint32_t S = 0;
+        if (no_sa) {
+            S = st.M;
+        } else if (st.has_cells) {
+            uint32_t next = C.bs->S_tot;
+            for (uint32_t g = f + 1; g < nf; ++g)
+                if (C.fs[g].has_cells) { next = C.fs[g].cell_begin; break; }
+            S = next - st.cell_begin;
+        }
+        uint32_t R = 0;
+        for (int k = 0; k < kRSlots; ++k) R += st.R[k];
         if (fr.moff && S <= fr.capacity) fr.moff[S] = st.M;
         *fr.count = S;
         *fr.status = (S > fr.capacity || (fr.mids && st.M > fr.member_capacity))
@@ -1135,7 +1483,7 @@ __device__ void ph_final(const Ctx& C, uint32_t, char*) {
         if (fr.info) {
             fr.info[0] = st.M;
             fr.info[1] = S;
-            fr.info[2] = st.R;
+            fr.info[2] = R;
             fr.info[3] = C.bs->key_bits;
         }
     }

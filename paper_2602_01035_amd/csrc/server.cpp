@@ -25,7 +25,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/fuseflow.h"
+#include "fuseflow.h"
 
 namespace {
 

@@ -54,9 +54,9 @@ def test_batched_matches_alone_and_oracle(ff, use_graph):
     ctx.close()
 
 
-@pytest.mark.parametrize("tuning", [dict(radix_bits=4, sort_items=4),
-                                    dict(radix_bits=6, sort_items=16),
-                                    dict(radix_bits=8, sort_items=8)])
+@pytest.mark.parametrize("tuning", [dict(radix_bits=6, sort_items=8),
+                                    dict(radix_bits=8, sort_items=16),
+                                    dict(radix_bits=10, sort_items=8)])
 def test_tuning_does_not_change_results(ff, tuning):
     print(f"[case] tuning {tuning}", flush=True)
     f = cached_frame("c2")
