@@ -361,8 +361,8 @@ class Context:
     def fuse_batch(self, frames: List[Dict], params: Optional[Params] = None,
                    outs: Optional[List[Output]] = None, stream=None,
                    members: bool = False) -> List[Output]:
-        """Several frames in one persistent launch (ff_fuse_batch).  Each frame is a dict with
-        cams, depth, conf and optional rgb."""
+        """Several frames in one batched call (ff_fuse_batch, replayed from a cached
+        graph).  Each frame is a dict with cams, depth, conf and optional rgb."""
         cf, keep = self._frames(frames)
         if outs is None:
             outs = []

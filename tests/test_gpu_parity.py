@@ -131,8 +131,8 @@ def test_batch_equals_single(ctx, ff):
 
 
 @pytest.mark.skip(reason="the single persistent launch that runs every phase in one kernel "
-                  "did not finish on the device in two runs; it is compiled out "
-                  "(FF_EXPERIMENTAL_PERSISTENT) until its cause is shown on the CPU")
+                  "did not finish on the device in two runs; it is not built until its "
+                  "cause is shown on the CPU (per-phase kernels under a graph replace it)")
 def test_persistent_single_launch(ctx, ff):
     raise AssertionError("not built")
 
