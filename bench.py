@@ -13,8 +13,12 @@ the 4 rigs (4 x 7,372,800 pixels).  Timed runs:
     previous to finish);
   * Poisson arrivals at 30 Hz per rig times each --rates multiplier: p50/p99 latency of
     both paths on the same trace;
-  * per-kernel times from HIP events on the plain path (roofline of the dominant kernel);
-  * the CPU oracle on one frame (cpu_baseline).
+Before them, every input frame goes once through ff_fuse (its M, S, R give the algorithmic
+bytes) and one frame is traced kernel by kernel (HIP events) to name the dominant kernel;
+during the timed serving run that kernel alone is timed by events on the lane streams
+(roofline).  After them, the CPU oracle runs on a bounded sample (cpu_baseline).
+--copy-calibration MiB first runs a plain elementwise copy (read N, write N bytes) so that
+hardware byte counters of the same profiled run can be scaled.
 Prints ONE JSON line.
 """
 from __future__ import annotations
@@ -77,6 +81,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="run a plain copy kernel of this size first (counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,6 +100,16 @@ def main():
     from synth import make_config
     from synth.scenes import poisson_arrivals
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 18                      # float32 elements
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)                              # reads 4n bytes, writes 4n
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {4 * n} bytes read + written")
+        del a, b
+
     # ------------------------------------------------------------------ inputs
     t0 = time.time()
     frames = {}            # (rig, f) -> host frame
@@ -108,54 +124,92 @@ def main():
     torch.cuda.synchronize()
 
     n_out = 16
-    outs = {rig: [ff.Output(P, rgb=True) for _ in range(n_out)] for rig in range(N_RIGS)}
     params = ff.Params()
     K = params.k_views
 
+    # ------------------------------------------------------------------ frame sizes + kernels
+    # every input frame once through ff_fuse: M, S, R per frame (for algorithmic bytes) and
+    # a per-kernel breakdown (HIP events on the call's stream) that names the dominant kernel
+    ctx = ff.Context(max_pixels=P, max_cameras=8)
+    stream = torch.cuda.current_stream()
+    sizes = {}
+    for key, d in devs.items():
+        o = ff.Output(P, rgb=True)
+        ctx.fuse(d["cams"], d["depth"], d["conf"], d["rgb"], out=o, stream=stream)
+        info = o.result()["info"]
+        sizes[key] = dict(P=P, M=int(info[0]), S=int(info[1]), R=int(info[2]),
+                          kb=4 if int(info[3]) <= 32 else 8)
+    d0 = devs[(0, 0)]
+    out0 = ff.Output(P, rgb=True)
+    ctx.trace(True)
+    n_tr = 10
+    for _ in range(n_tr):
+        ctx.fuse(d0["cams"], d0["depth"], d0["conf"], d0["rgb"], out=out0, stream=stream)
+    tr = ctx.trace_read()
+    ctx.trace(False)
+    ctx.close()
+    z = sizes[(0, 0)]
+    kernels = {}
+    for name, v in tr["kernels"].items():
+        b = kernel_bytes(name, P, z["M"], z["S"], z["R"], K, z["kb"])
+        kernels[name] = dict(slot=v["slot"], mean_ms=round(v["mean_ms"], 5),
+                             ms_per_frame=round(v["total_ms"] / max(1, tr["calls"]), 5),
+                             alg_bytes=b,
+                             gbs=round(b / (v["mean_ms"] * 1e-3) / 1e9, 1) if b else None)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_frame"])
+    dom_slot = kernels[dom]["slot"]
+    frame_ms_kernels = sum(v["ms_per_frame"] for v in kernels.values())
+    log(f"dominant kernel {dom} ({kernels[dom]['mean_ms'] * 1e3:.1f} us of "
+        f"{frame_ms_kernels * 1e3:.1f} us per frame)")
+
+    outs = {rig: [ff.Output(P, rgb=True) for _ in range(n_out)] for rig in range(N_RIGS)}
+
     def step_frames(step):
-        return [(rig, devs[(rig, step % args.frames_per_rig)]) for rig in range(N_RIGS)]
+        f = step % args.frames_per_rig
+        return [(rig, f) for rig in range(N_RIGS)]
 
     srv = ff.Server(hbm_budget_bytes=8 << 30, lanes=args.lanes, max_batch_frames=args.batch,
                     max_pending=1 << 20)
     plain = ff.Server(hbm_budget_bytes=8 << 30, plain=True, max_pending=1 << 20)
 
     def saturate(server, steps):
-        """steps x 4 frames submitted back to back; returns (seconds, frames)."""
+        """steps x 4 frames submitted back to back; returns (seconds, frames, alg bytes of
+        the dominant kernel over those frames)."""
         server.reset_stats()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        k = 0
+        k, nbytes = 0, 0
         for s in range(steps):
-            for rig, d in step_frames(s):
-                server.submit(rig, d, outs[rig][k % n_out], params)
+            for rig, f in step_frames(s):
+                server.submit(rig, devs[(rig, f)], outs[rig][s % n_out], params)
+                z = sizes[(rig, f)]
+                nbytes += kernel_bytes(dom, z["P"], z["M"], z["S"], z["R"], K, z["kb"])
                 k += 1
         server.drain()
         torch.cuda.synchronize()
-        return time.perf_counter() - t, k
+        return time.perf_counter() - t, k, nbytes
 
     # ------------------------------------------------------------------ warmup + throughput
     saturate(srv, args.warmup)
     saturate(plain, args.warmup)
-    dt_srv, n_srv = saturate(srv, args.steps)
+    srv.probe(dom_slot)                     # events around the dominant kernel, every batch
+    dt_srv, n_srv, dom_bytes = saturate(srv, args.steps)
+    probe = srv.probe_read()
+    srv.probe(-1)
     st_srv = srv.stats()
-    dt_pl, n_pl = saturate(plain, args.steps)
+    dt_pl, n_pl, _ = saturate(plain, args.steps)
     st_pl = plain.stats()
     px_srv = n_srv * P / dt_srv
     px_pl = n_pl * P / dt_pl
     log(f"serving {px_srv / 1e9:.2f} Gpx/s ({dt_srv / args.steps * 1e3:.3f} ms/step, "
         f"{st_srv['mean_batch_frames']:.2f} frames/batch); plain {px_pl / 1e9:.2f} Gpx/s")
+    assert probe["frames"] == n_srv, probe
 
-    # fused points of one step (cells per frame), read back after the run
-    S_frames, info = [], []
-    for rig in range(N_RIGS):
-        r = outs[rig][0].result()
-        S_frames.append(r["count"])
-        info.append(r["info"])
-    M_mean = float(np.mean([i[0] for i in info]))
-    S_mean = float(np.mean([i[1] for i in info]))
-    R_mean = float(np.mean([i[2] for i in info]))
-    key_bits = int(info[0][3])
-    fused_per_s = S_mean * n_srv / dt_srv
+    M_mean = float(np.mean([z["M"] for z in sizes.values()]))
+    S_mean = float(np.mean([z["S"] for z in sizes.values()]))
+    R_mean = float(np.mean([z["R"] for z in sizes.values()]))
+    S_timed = sum(sizes[(rig, f)]["S"] for s in range(args.steps) for rig, f in step_frames(s))
+    fused_per_s = S_timed / dt_srv
 
     # ------------------------------------------------------------------ latency traces
     latency = []
@@ -189,42 +243,26 @@ def main():
     srv.close()
     plain.close()
 
-    # ------------------------------------------------------------------ per-kernel times
-    ctx = ff.Context(max_pixels=P, max_cameras=8)
-    stream = torch.cuda.current_stream()
-    d0 = devs[(0, 0)]
-    out0 = ff.Output(P, rgb=True)
-    for _ in range(2):
-        ctx.fuse(d0["cams"], d0["depth"], d0["conf"], d0["rgb"], out=out0)
-    ctx.trace(True)
-    n_tr = 10
-    for _ in range(n_tr):
-        ctx.fuse(d0["cams"], d0["depth"], d0["conf"], d0["rgb"], out=out0, stream=stream)
-    tr = ctx.trace_read()
-    ctx.trace(False)
-    r0 = out0.result()
-    M0, S0, R0, kb0 = int(r0["info"][0]), int(r0["info"][1]), int(r0["info"][2]), int(r0["info"][3])
-    kb = 4 if kb0 <= 32 else 8
-    kernels = {}
-    for name, v in tr["kernels"].items():
-        b = kernel_bytes(name, P, M0, S0, R0, K, kb)
-        per_call_ms = v["total_ms"] / max(1, tr["calls"])
-        kernels[name] = dict(mean_ms=round(v["mean_ms"], 5), ms_per_frame=round(per_call_ms, 5),
-                             alg_bytes=b, gbs=round(b / (v["mean_ms"] * 1e-3) / 1e9, 1) if b else None)
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_frame"])
-    frame_ms_kernels = sum(v["ms_per_frame"] for v in kernels.values())
-    dk = kernels[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4) if dk["gbs"] else None,
-                "traffic": None, "alg_bytes_per_launch": dk["alg_bytes"],
-                "mean_launch_ms": dk["mean_ms"]}
-    B_frame = frame_alg_bytes(P, M0, S0, R0, K)
+    # ------------------------------------------------------------------ roofline
+    # dominant kernel over the timed serving region: algorithmic bytes of the frames it
+    # processed / its summed duration (HIP events on the lane streams it ran on)
+    mean_launch_ms = probe["total_ms"] / max(1, probe["launches"])
+    achieved = dom_bytes / (probe["total_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "alg_bytes_per_launch": dom_bytes / max(1, probe["launches"]),
+                "mean_launch_ms": round(mean_launch_ms, 5), "launches": probe["launches"],
+                "frames_per_launch": probe["frames"] / max(1, probe["launches"])}
+    B_frame = frame_alg_bytes(P, z["M"], z["S"], z["R"], K)
+    B_timed = sum(frame_alg_bytes(P, sizes[k]["M"], sizes[k]["S"], sizes[k]["R"], K)
+                  for s in range(args.steps) for k in step_frames(s))
     frame_roofline = {
         "alg_bytes_per_frame": B_frame,
         "serving_ms_per_frame": dt_srv / n_srv * 1e3,
-        "frac_serving": round(B_frame * n_srv / dt_srv / (HBM_PEAK_GBS * 1e9), 4),
+        "frac_serving": round(B_timed / dt_srv / (HBM_PEAK_GBS * 1e9), 4),
         "plain_ms_per_frame": dt_pl / n_pl * 1e3,
-        "frac_plain": round(B_frame * n_pl / dt_pl / (HBM_PEAK_GBS * 1e9), 4),
+        "frac_plain": round(B_timed / dt_pl / (HBM_PEAK_GBS * 1e9), 4),
         "kernel_ms_per_frame": round(frame_ms_kernels, 4),
     }
 
@@ -232,16 +270,18 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import core as O
-        fr = frames[(0, 0)]
+        sample = [(0, f) for f in range(min(2, args.frames_per_rig))]
         c0, w0 = time.process_time(), time.perf_counter()
-        O.fuse_frame(fr)
+        for key in sample:
+            O.fuse_frame(frames[key])
         wall = time.perf_counter() - w0
         cpu_t = time.process_time() - c0
-        cpu = {"value": P / wall, "unit": "px/s", "cores": max(1, round(cpu_t / wall)),
-               "kind": "oracle",
-               "sample": f"1 frame of rig 0 (8 x 1280x720 = {P} px) through the NumPy oracle, "
-                         f"{wall:.1f} s wall, {os.cpu_count()} host CPUs visible"}
-        log(f"oracle {wall:.1f} s per frame")
+        cpu = {"value": len(sample) * P / wall, "unit": "px/s",
+               "cores": max(1, round(cpu_t / wall)), "kind": "oracle",
+               "sample": f"{len(sample)} frame(s) of rig 0 (8 x 1280x720 = {P} px each) "
+                         f"through the NumPy oracle, {wall:.1f} s wall, "
+                         f"{os.cpu_count()} host CPUs visible"}
+        log(f"oracle {wall / len(sample):.1f} s per frame")
 
     line = {
         "metric": METRIC, "value": px_srv, "unit": "px/s", "n_gpus": 1, "steps": args.steps,
@@ -261,7 +301,7 @@ def main():
                   "p50_ms": st_pl["p50_ms"], "p99_ms": st_pl["p99_ms"]},
         "speedup_serving_vs_plain": px_srv / px_pl,
         "fused_points_per_s": fused_per_s,
-        "frame_sizes": {"P": P, "M": M_mean, "S": S_mean, "R": R_mean, "key_bits": key_bits},
+        "frame_sizes": {"P": P, "M": M_mean, "S": S_mean, "R": R_mean},
         "latency": latency,
         "kernels": kernels,
         "roofline": roofline,

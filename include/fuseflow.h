@@ -190,6 +190,23 @@ ff_status ff_trace_enable(ff_context* ctx, int32_t on);   /* on resets the total
 ff_status ff_trace_read(ff_context* ctx, ff_trace* out);  /* waits for the timed work */
 const char* ff_trace_slot_name(int32_t slot);
 
+/* Probe: the duration of ONE kernel (a trace slot) in every call, graph replays included.
+ * Events are recorded on the call's stream just before and after that kernel; in a graph
+ * replay the graph is split around it (the launches before and after it are replayed from
+ * graphs cached per segment), so the rest of the call keeps its launch structure.  While
+ * per-kernel tracing is on, the probe records nothing.  Totals accumulate from
+ * ff_probe_enable (which resets them; slot -1 switches the probe off) until the next enable. */
+typedef struct ff_probe {
+    int32_t slot;                 /* probed trace slot, -1 = off */
+    int32_t reserved;
+    uint64_t launches;            /* timed launches of that kernel */
+    uint64_t frames;              /* frames those launches processed */
+    uint64_t pixels;              /* input pixels of those frames */
+    double total_ms;              /* summed kernel time */
+} ff_probe;
+ff_status ff_probe_enable(ff_context* ctx, int32_t slot); /* waits for recorded launches */
+ff_status ff_probe_read(ff_context* ctx, ff_probe* out);  /* waits for recorded launches */
+
 /* ------------------------------------------------------------------------------ serving
  * A streaming loop over several rigs (the paper's per-frame statelessness, Sec. II.1, is
  * what makes frames of different rigs independent work).  Frames are admitted as they
@@ -252,6 +269,10 @@ ff_status ff_server_drain(ff_server* s);
 ff_status ff_server_stats(const ff_server* s, ff_stats* st);
 /* Forget completed frames' latencies (stats restart from zero). */
 ff_status ff_server_reset_stats(ff_server* s);
+/* The probe on every lane (see ff_probe_enable); read sums the lanes.  Both wait for the
+ * lanes' recorded launches to finish. */
+ff_status ff_server_probe_enable(ff_server* s, int32_t slot);
+ff_status ff_server_probe_read(ff_server* s, ff_probe* out);
 
 #ifdef __cplusplus
 }

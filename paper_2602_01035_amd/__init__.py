@@ -69,6 +69,12 @@ class ff_trace(ctypes.Structure):
                 ("calls", ctypes.c_uint64)]
 
 
+class ff_probe(ctypes.Structure):
+    _fields_ = [("slot", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("launches", ctypes.c_uint64), ("frames", ctypes.c_uint64),
+                ("pixels", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
 class ff_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("lanes", ctypes.c_int32),
                 ("max_batch_frames", ctypes.c_int32), ("max_cameras", ctypes.c_int32),
@@ -108,6 +114,8 @@ EXPORTS = {
     "ff_trace_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ff_trace_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_trace)]),
     "ff_trace_slot_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ff_probe_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ff_probe_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_probe)]),
     "ff_server_config_default": (None, [ctypes.POINTER(ff_server_config)]),
     "ff_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                         ctypes.POINTER(ff_server_config)]),
@@ -123,6 +131,8 @@ EXPORTS = {
     "ff_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
     "ff_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_stats)]),
     "ff_server_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
+    "ff_server_probe_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ff_server_probe_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_probe)]),
 }
 
 
@@ -170,6 +180,12 @@ class Params:
 def _check(status: int, where: str):
     if status != FF_OK:
         raise FuseFlowError(status, where)
+
+
+def _probe_dict(p: ff_probe) -> Dict:
+    return dict(slot=int(p.slot), launches=int(p.launches), frames=int(p.frames),
+                pixels=int(p.pixels), total_ms=float(p.total_ms),
+                mean_ms=float(p.total_ms) / p.launches if p.launches else 0.0)
 
 
 def _camera(cam) -> ff_camera:
@@ -309,9 +325,18 @@ class Context:
         for s in range(32):
             if t.launches[s]:
                 out[_lib.ff_trace_slot_name(s).decode()] = dict(
-                    total_ms=t.total_ms[s], launches=int(t.launches[s]),
+                    slot=s, total_ms=t.total_ms[s], launches=int(t.launches[s]),
                     mean_ms=t.total_ms[s] / t.launches[s])
         return dict(calls=int(t.calls), kernels=out)
+
+    def probe(self, slot: int):
+        """Time trace slot `slot` in every later call (-1: off); resets the totals."""
+        _check(_lib.ff_probe_enable(self.h, int(slot)), "ff_probe_enable")
+
+    def probe_read(self) -> Dict:
+        p = ff_probe()
+        _check(_lib.ff_probe_read(self.h, ctypes.byref(p)), "ff_probe_read")
+        return _probe_dict(p)
 
     # -- marshalling
     @staticmethod
@@ -465,6 +490,15 @@ class Server:
 
     def reset_stats(self):
         _check(_lib.ff_server_reset_stats(self.h), "ff_server_reset_stats")
+
+    def probe(self, slot: int):
+        """Time trace slot `slot` in every later batch on every lane (-1: off)."""
+        _check(_lib.ff_server_probe_enable(self.h, int(slot)), "ff_server_probe_enable")
+
+    def probe_read(self) -> Dict:
+        p = ff_probe()
+        _check(_lib.ff_server_probe_read(self.h, ctypes.byref(p)), "ff_server_probe_read")
+        return _probe_dict(p)
 
 
 def to_device(frame, device="cuda", with_rgb=True) -> Dict:

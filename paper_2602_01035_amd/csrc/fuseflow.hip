@@ -138,6 +138,17 @@ struct ff_context {
     std::vector<int> tslot;
     size_t tused = 0;
     ff_trace tacc{};
+    // timing of one kernel inside every call, graph replays included (events on the
+    // call's stream just before and after that kernel)
+    int32_t probe_slot = -1;
+    struct ProbeRec {
+        hipEvent_t a, b;
+        uint32_t frames;
+        uint64_t pixels;
+    };
+    std::vector<ProbeRec> probe_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> probe_free;
+    ff_probe pacc{};
 };
 
 namespace {
@@ -450,6 +461,52 @@ ff_status trace_mark(ff_context* c, int slot, bool begin, hipStream_t s) {
     return FF_OK;
 }
 
+// harvest finished probe records in call order; `all` waits for every one
+ff_status probe_collect(ff_context* c, bool all) {
+    size_t done = 0;
+    ff_status st = FF_OK;
+    for (; done < c->probe_pending.size(); ++done) {
+        const ff_context::ProbeRec& r = c->probe_pending[done];
+        hipError_t q = all ? hipEventSynchronize(r.b) : hipEventQuery(r.b);
+        if (q == hipErrorNotReady) break;
+        float ms = 0;
+        if (q != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            (void)hipGetLastError();
+            st = FF_ERR_HIP;
+        } else {
+            c->pacc.total_ms += ms;
+            c->pacc.launches += 1;
+            c->pacc.frames += r.frames;
+            c->pacc.pixels += r.pixels;
+        }
+        c->probe_free.push_back({r.a, r.b});
+    }
+    c->probe_pending.erase(c->probe_pending.begin(), c->probe_pending.begin() + done);
+    return st;
+}
+
+ff_status probe_mark(ff_context* c, bool begin, hipStream_t s, uint32_t frames,
+                     uint64_t pixels) {
+    if (begin) {
+        if (c->probe_free.empty()) {
+            hipEvent_t a, b;
+            FF_HIP(hipEventCreate(&a));
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return FF_ERR_HIP;
+            }
+            c->probe_free.push_back({a, b});
+        }
+        const auto ev = c->probe_free.back();
+        c->probe_free.pop_back();
+        c->probe_pending.push_back({ev.first, ev.second, frames, pixels});
+        FF_HIP(hipEventRecord(ev.first, s));
+    } else {
+        FF_HIP(hipEventRecord(c->probe_pending.back().b, s));
+    }
+    return FF_OK;
+}
+
 template <int ITEMS>
 void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, bool wide_views, hipStream_t s) {
     const size_t smem = smem_for(L.kind, ITEMS, ncams);
@@ -532,6 +589,42 @@ ff_status run_graph(ff_context* c, const Ctx& C, const Plan& plan, const std::st
     return FF_OK;
 }
 
+// The plan with the probed kernel launched on its own between events; the launches
+// around it run as before (replayed from graphs cached per segment, or enqueued).
+ff_status run_probed(ff_context* c, const Ctx& C, const Plan& plan, const std::string& shape,
+                     hipStream_t s, bool graph, uint32_t frames, uint64_t pixels) {
+    Plan seg;
+    seg.ncams = plan.ncams;
+    seg.wide_views = plan.wide_views;
+    int nseg = 0;
+    auto flush = [&]() -> ff_status {
+        if (seg.launches.empty()) return FF_OK;
+        ff_status st = graph ? run_graph(c, C, seg,
+                                         shape + "|seg" + std::to_string(nseg) + "|probe" +
+                                             std::to_string(c->probe_slot),
+                                         s)
+                             : dispatch_plain(c, C, seg, s);
+        ++nseg;
+        seg.launches.clear();
+        return st;
+    };
+    for (const Launch& L : plan.launches) {
+        if (trace_slot(L) != c->probe_slot) {
+            seg.launches.push_back(L);
+            continue;
+        }
+        ff_status st = flush();
+        if (st != FF_OK) return st;
+        if ((st = probe_mark(c, true, s, frames, pixels)) != FF_OK) return st;
+        seg.launches.push_back(L);
+        st = dispatch_plain(c, C, seg, s);
+        seg.launches.clear();
+        if (st != FF_OK) return st;
+        if ((st = probe_mark(c, false, s, frames, pixels)) != FF_OK) return st;
+    }
+    return flush();
+}
+
 ff_status set_smem_limits() {
     static std::once_flag once;
     static ff_status result = FF_OK;
@@ -592,6 +685,8 @@ void ff_context_destroy(ff_context* c) {
     if (c->have_last) (void)hipEventSynchronize(c->last);
     drop_graphs(c);
     for (auto& e : c->tev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    (void)probe_collect(c, true);
+    for (auto& e : c->probe_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (void* p : c->allocs) (void)hipFree(p);
     for (int i = 0; i < kStageSlots; ++i) {
         if (c->h_stage[i]) (void)hipHostFree(c->h_stage[i]);
@@ -698,13 +793,26 @@ static ff_status fuse_impl(ff_context* c, int32_t n_frames, const ff_frame* fram
     ff_status st = build_desc(c, n_frames, frames, params, outs, c->h_stage[slot], plan, shape);
     if (st != FF_OK) return st;
     if (c->trace && (st = trace_collect(c)) != FF_OK) return st;
+    if (!c->probe_pending.empty() &&
+        (st = probe_collect(c, c->probe_pending.size() >= 256)) != FF_OK)
+        return st;
     const Ctx C = make_ctx(c);
     // calls on one context share its workspace: order this one after the previous one
     if (c->have_last) FF_HIP(hipStreamWaitEvent(s, c->last, 0));
     FF_HIP(hipMemcpyAsync(c->d_desc, c->h_stage[slot], c->desc_bytes, hipMemcpyHostToDevice, s));
     FF_HIP(hipEventRecord(c->stage_ev[slot], s));
-    if (batched && c->tune.use_graph && !c->trace) st = run_graph(c, C, plan, shape, s);
-    else st = dispatch_plain(c, C, plan, s);
+    const bool graph = batched && c->tune.use_graph && !c->trace;
+    if (c->probe_slot >= 0 && !c->trace) {
+        uint64_t px = 0;
+        for (int32_t f = 0; f < n_frames; ++f)
+            for (int32_t k = 0; k < frames[f].n_cams; ++k)
+                px += (uint64_t)frames[f].cams[k].width * (uint64_t)frames[f].cams[k].height;
+        st = run_probed(c, C, plan, shape, s, graph, (uint32_t)n_frames, px);
+    } else if (graph) {
+        st = run_graph(c, C, plan, shape, s);
+    } else {
+        st = dispatch_plain(c, C, plan, s);
+    }
     if (st != FF_OK) return st;
     FF_HIP(hipGetLastError());
     FF_HIP(hipEventRecord(c->last, s));
@@ -740,6 +848,24 @@ ff_status ff_trace_read(ff_context* c, ff_trace* out) {
     DeviceGuard g(c->device);
     ff_status st = trace_collect(c);
     *out = c->tacc;
+    return st;
+}
+
+ff_status ff_probe_enable(ff_context* c, int32_t slot) {
+    if (!c || slot < -1 || slot >= FF_TRACE_SLOTS) return FF_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    ff_status st = probe_collect(c, true);
+    c->probe_slot = slot;
+    c->pacc = ff_probe{};
+    c->pacc.slot = slot;
+    return st;
+}
+
+ff_status ff_probe_read(ff_context* c, ff_probe* out) {
+    if (!c || !out) return FF_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    ff_status st = probe_collect(c, true);
+    *out = c->pacc;
     return st;
 }
 

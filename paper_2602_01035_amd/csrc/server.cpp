@@ -373,4 +373,34 @@ ff_status ff_server_reset_stats(ff_server* s) {
     return FF_OK;
 }
 
+ff_status ff_server_probe_enable(ff_server* s, int32_t slot) {
+    if (!s) return FF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);    // the scheduler launches under this lock
+    ff_status st = FF_OK;
+    for (Lane& L : s->lanes) {
+        const ff_status e = ff_probe_enable(L.ctx, slot);
+        if (e != FF_OK) st = e;
+    }
+    return st;
+}
+
+ff_status ff_server_probe_read(ff_server* s, ff_probe* out) {
+    if (!s || !out) return FF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->slot = -1;
+    ff_status st = FF_OK;
+    for (Lane& L : s->lanes) {
+        ff_probe p{};
+        const ff_status e = ff_probe_read(L.ctx, &p);
+        if (e != FF_OK) st = e;
+        out->slot = p.slot;
+        out->launches += p.launches;
+        out->frames += p.frames;
+        out->pixels += p.pixels;
+        out->total_ms += p.total_ms;
+    }
+    return st;
+}
+
 }  // extern "C"

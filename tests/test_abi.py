@@ -60,6 +60,42 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(ff.ff_frame) == 8 + 2 * 8
 
 
+STRUCTS = ("ff_camera", "ff_view", "ff_params", "ff_output", "ff_frame", "ff_tuning",
+           "ff_trace", "ff_probe", "ff_server_config", "ff_stats")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Size and every field offset of each ctypes struct against gcc on the header."""
+    import shutil
+    import subprocess
+    import paper_2602_01035_amd as ff
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fuseflow.h"',
+             'int main(void) {']
+    for name in STRUCTS:
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in getattr(ff, name)._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                             text=True).stdout.splitlines():
+        a, b, v = ln.split()
+        got[(a, b)] = int(v)
+    for name in STRUCTS:
+        cls = getattr(ff, name)
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
+
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_invalid_arguments_rejected_without_gpu_work():
     import paper_2602_01035_amd as ff

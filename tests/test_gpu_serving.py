@@ -131,3 +131,42 @@ def test_server_back_pressure(ff):
     srv.drain()
     assert srv.stats()["frames"] == 2
     srv.close()
+
+
+@pytest.mark.parametrize("slot", [13, 18])
+def test_probe_keeps_results_and_counts_launches(ff, slot):
+    """Timing one kernel splits the cached graph around it; results must not change."""
+    print(f"[case] probe slot {slot}", flush=True)
+    frames = _frames()[:3]
+    devs = [ff.to_device(f) for f in frames]
+    ctx = ff.Context(max_pixels=4_000_000, max_cameras=16, max_frames=4)
+    ref = [o.result() for o in ctx.fuse_batch(devs)]
+    ctx.probe(slot)
+    for rep in range(3):
+        outs = ctx.fuse_batch(devs)
+        for g, r in zip((o.result() for o in outs), ref):
+            for k in KEYS:
+                assert np.array_equal(g[k], r[k]), (rep, k)
+    p = ctx.probe_read()
+    assert p["slot"] == slot and p["launches"] == 3 and p["frames"] == 9
+    assert p["pixels"] == 3 * sum(f.pixels for f in frames)
+    assert 0 < p["mean_ms"] < 1000
+    ctx.probe(-1)
+    ctx.fuse_batch(devs)
+    assert ctx.probe_read()["launches"] == 0
+    ctx.close()
+
+
+def test_server_probe(ff):
+    print("[case] server probe", flush=True)
+    frames = _frames()
+    devs = [ff.to_device(f) for f in frames]
+    srv = ff.Server(hbm_budget_bytes=2 << 30, lanes=2, max_batch_frames=4)
+    srv.probe(13)
+    for i, d in enumerate(devs):
+        srv.submit(0, d, ff.Output(sum(c.width * c.height for c in d["cams"])))
+    srv.drain()
+    p = srv.probe_read()
+    assert p["frames"] == len(devs) and p["launches"] == srv.stats()["batches"]
+    assert p["total_ms"] > 0
+    srv.close()
