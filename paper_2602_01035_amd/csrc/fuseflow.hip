@@ -76,7 +76,7 @@ size_t down_smem(int items) {
     return kt * 8 + kt * 4 + (4 + 2) * kMaxDigits * 4 + 32 + kMaxBatchCams * 4;
 }
 size_t cells_smem(uint32_t ncams) {
-    return sizeof(CellsShared) + (ncams <= (uint32_t)kLdsCams ? ncams * sizeof(CamLite) : 0);
+    return cells_layout(ncams, ncams <= (uint32_t)kLdsCams).total;
 }
 size_t smem_for(uint32_t kind, int items, uint32_t ncams) {
     switch (kind) {
@@ -355,6 +355,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
         df.xyz = o.xyz; df.weight = o.weight; df.rgb = o.rgb;
         df.n_members = o.n_members; df.reps = o.reps; df.keys = o.keys;
         df.moff = o.member_offsets; df.mids = o.member_ids;
+        if (o.member_ids) H->any_mids = 1;
         df.capacity = o.capacity; df.member_capacity = o.member_capacity;
         df.count = o.count; df.status = o.status; df.info = o.info;
     }
@@ -383,7 +384,8 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     const uint32_t KT = (uint32_t)(kBlock * c->tune.sort_items);
     H->sort_items = (uint32_t)c->tune.sort_items;
     H->n_sort_tiles = (uint32_t)std::max<uint64_t>(1, (P + KT - 1) / KT);
-    H->n_cell_items = (uint32_t)std::min<uint64_t>(8192, std::max<uint64_t>(1, (P + 1023) / 1024));
+    // per-cell phase: waves walk 16-cell chunks; about 8 workgroups per CU at most
+    H->n_cell_items = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(1, (P + 4095) / 4096));
     H->max_radix_bits = (uint32_t)c->tune.radix_bits;
     // widest possible dense key: frames x coarse cells x 8^Lmax
     const uint32_t bits_max = (uint32_t)(ilog2((uint32_t)n_frames) + 3 * H->prm.log2G +
@@ -635,6 +637,11 @@ ff_status set_smem_limits() {
         };
         setk((const void*)k_phase<PH_RADIX_DOWN, 8>, down_smem(8));
         setk((const void*)k_phase<PH_RADIX_DOWN, 16>, down_smem(16));
+        const size_t cs = std::max(cells_smem((uint32_t)kLdsCams), cells_smem((uint32_t)kMaxBatchCams));
+        setk((const void*)k_cells<3, true>, cs);
+        setk((const void*)k_cells<3, false>, cs);
+        setk((const void*)k_cells<kMaxK - 1, true>, cs);
+        setk((const void*)k_cells<kMaxK - 1, false>, cs);
     });
     return result;
 }

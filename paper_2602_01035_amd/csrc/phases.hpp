@@ -1120,13 +1120,41 @@ struct Cand {
     Pt p;
 };
 
+// Per-wave staging of the per-cell phase: 64 cells and their up to 192 representatives.
+constexpr int kStageCells = 64;
+struct WaveStage {
+    uint32_t start[kStageCells];
+    uint32_t end[kStageCells];               // start == end: no output for this slot
+    uint32_t sid[3 * kStageCells];           // representative: sorted position, then pixel id
+    float sC[3 * kStageCells];
+    float px[3 * kStageCells], py[3 * kStageCells], pz[3 * kStageCells];
+    uint32_t rgb[3 * kStageCells];
+    uint32_t ex_lo[3 * kStageCells], ex_hi[3 * kStageCells];   // -ln V as a double
+    uint8_t list[3 * kStageCells];           // compacted representative slots
+    uint8_t bad[kStageCells];
+};
+constexpr int kCellsStageBytes = (kBlock / 64) * (int)sizeof(WaveStage);
+
+// LDS of the per-cell phase: this header, then the cameras' pixel offsets, then (when few
+// enough) the camera records, then one stage per wave.
 struct CellsShared {
-    uint32_t cam_pix[kMaxBatchCams];            // batch pix_off per camera (sorted)
     uint32_t fpix[kMaxFrames];                  // frame pix_begin
     uint32_t key_begin[kMaxFrames];             // frame's first sorted/compacted position
     uint32_t cell_begin[kMaxFrames];            // frame's first global cell
-    uint32_t w[8];
+    uint32_t rcount[kMaxFrames];                // representatives per frame (this workgroup)
 };
+
+struct CellsLayout {
+    uint32_t cam_pix, cams, stage, total;       // byte offsets, total bytes
+};
+__host__ __device__ inline CellsLayout cells_layout(uint32_t ncams, bool lds_cams) {
+    CellsLayout l;
+    l.cam_pix = (uint32_t)sizeof(CellsShared);
+    l.cams = (l.cam_pix + 4 * ncams + 15u) & ~15u;
+    l.stage = (l.cams + (lds_cams ? ncams * (uint32_t)sizeof(CamLite) : 0u) + 15u) & ~15u;
+    l.total = l.stage + (uint32_t)kCellsStageBytes;
+    return l;
+}
 
 struct CellCtx {
     const Ctx& C;
@@ -1248,26 +1276,95 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const P
     return s / ((double)m * (sig * sig));
 }
 
-__device__ __forceinline__ void emit_cell(const CamLite* cams, const DevFrame& fr, uint32_t o, Cand* rep,
-                          int nrep, const double* expo, uint32_t nmem, uint64_t key) {
-    // joint weights w = C V (Eq. 10) and the normalised weighted mean (Eq. 11); when every
-    // weight underflows the same mean is taken in the log domain (softmax of ln C - ln V^-1)
-    double wv[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        if (r < nrep) wv[r] = (double)rep[r].C * exp(-expo[r]);
-        wsum += wv[r];
+// ---------------------------------------------------------------- quad exchange
+// Four consecutive lanes of a wave work on one cell.  DPP quad permutations move values
+// between them; every use sits where all four lanes of the quad are active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t qmov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float qmovf(float v) {
+    return __uint_as_float(qmov<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double qmovd(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = qmov<CTRL>((uint32_t)u), hi = qmov<CTRL>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+constexpr int kQuadXor1 = 0xB1;                 // lanes [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;                 // lanes [2, 3, 0, 1]
+template <int R> struct QuadBcast { static constexpr int ctrl = R * 0x55; };   // [R, R, R, R]
+
+// insert c into the sorted list of the best n <= 3 members (full order)
+__device__ __forceinline__ void top3_insert(const CellCtx& X, Cand* rep, int& n, Cand& c) {
+    if (n == 3 && !rank_before(X, c, rep[2])) return;
+    if (n < 1 || rank_before(X, c, rep[0])) {
+        rep[2] = rep[1]; rep[1] = rep[0]; rep[0] = c;
+    } else if (n < 2 || rank_before(X, c, rep[1])) {
+        rep[2] = rep[1]; rep[1] = c;
+    } else {
+        rep[2] = c;
     }
+    if (n < 3) ++n;
+}
+
+// The best three members by confidence alone (sorted positions k).  `tie` is set whenever
+// a confidence equal to a kept one is met: only then can the position/pixel tie-break of
+// the full order change the result, and the caller ranks that cell again in full.
+struct Top3 {
+    float C0, C1, C2;
+    uint32_t k0, k1, k2;
+    int n;
+    bool tie;
+};
+
+__device__ __forceinline__ void top3c_insert(Top3& t, float c, uint32_t k) {
+    if ((t.n > 0 && c == t.C0) || (t.n > 1 && c == t.C1) || (t.n > 2 && c == t.C2)) t.tie = true;
+    if (t.n == 3 && !(c > t.C2)) return;
+    if (t.n < 1 || c > t.C0) {
+        t.C2 = t.C1; t.k2 = t.k1; t.C1 = t.C0; t.k1 = t.k0; t.C0 = c; t.k0 = k;
+    } else if (t.n < 2 || c > t.C1) {
+        t.C2 = t.C1; t.k2 = t.k1; t.C1 = c; t.k1 = k;
+    } else {
+        t.C2 = c; t.k2 = k;
+    }
+    if (t.n < 3) ++t.n;
+}
+
+// merge the partner lane's list (disjoint members) into this lane's
+template <int CTRL>
+__device__ __forceinline__ void top3c_merge(Top3& t) {
+    const int pn = (int)qmov<CTRL>((uint32_t)t.n | (t.tie ? 4u : 0u));
+    const float c0 = qmovf<CTRL>(t.C0), c1 = qmovf<CTRL>(t.C1), c2 = qmovf<CTRL>(t.C2);
+    const uint32_t k0 = qmov<CTRL>(t.k0), k1 = qmov<CTRL>(t.k1), k2 = qmov<CTRL>(t.k2);
+    if (pn & 4) t.tie = true;
+    if ((pn & 3) > 0) top3c_insert(t, c0, k0);
+    if ((pn & 3) > 1) top3c_insert(t, c1, k1);
+    if ((pn & 3) > 2) top3c_insert(t, c2, k2);
+}
+
+// Output of one cell from its representatives' values (lane 0 of the quad): joint weights
+// w = C V (Eq. 10) and the normalised weighted mean (Eq. 11); when every weight underflows
+// the same mean is taken in the log domain (softmax of ln C - ln V^-1).
+__device__ __forceinline__ void emit_cell(const DevFrame& fr, uint32_t o, int nrep,
+                                          const float* Cr, const Pt* pr, const double* expo,
+                                          const double* wv, const uint32_t* rgb3,
+                                          const uint32_t* idr, uint32_t nmem) {
+    double wsum = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) wsum += r < nrep ? wv[r] : 0.0;
     double pis[3] = {0.0, 0.0, 0.0};
     if (wsum > 1e-280) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) pis[r] = wv[r] / wsum;
+        for (int r = 0; r < 3; ++r) pis[r] = (r < nrep ? wv[r] : 0.0) / wsum;
     } else {
         double a[3] = {0.0, 0.0, 0.0}, amax = -INFINITY, se = 0.0;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             if (r >= nrep) continue;
-            a[r] = log((double)rep[r].C) - expo[r];
+            a[r] = log((double)Cr[r]) - expo[r];
             amax = a[r] > amax ? a[r] : amax;
         }
 #pragma unroll
@@ -1285,16 +1382,12 @@ __device__ __forceinline__ void emit_cell(const CamLite* cams, const DevFrame& f
     for (int r = 0; r < 3; ++r) {
         const double pi = pis[r];
         if (r < nrep) {
-            x += pi * (double)rep[r].p.x;
-            y += pi * (double)rep[r].p.y;
-            z += pi * (double)rep[r].p.z;
-            if (rgb) {
-                const CamLite& cm = cams[rep[r].cam];
-                const auto px = glob(cm.rgb + (uint64_t)(rep[r].id - cm.pix_off) * 3);
-                cr += pi * (double)px[0];
-                cg += pi * (double)px[1];
-                cb += pi * (double)px[2];
-            }
+            x += pi * (double)pr[r].x;
+            y += pi * (double)pr[r].y;
+            z += pi * (double)pr[r].z;
+            cr += pi * (double)(rgb3[r] & 0xFFu);
+            cg += pi * (double)(rgb3[r] >> 8 & 0xFFu);
+            cb += pi * (double)(rgb3[r] >> 16 & 0xFFu);
         } else {
             x += pi * 0.0; y += pi * 0.0; z += pi * 0.0;
         }
@@ -1316,14 +1409,28 @@ __device__ __forceinline__ void emit_cell(const CamLite* cams, const DevFrame& f
     if (fr.reps) {
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            glob(fr.reps)[(uint64_t)o * 3 + r] = r < nrep ? rep[r].id - fr.pix_begin : kPad;
+            glob(fr.reps)[(uint64_t)o * 3 + r] = r < nrep ? idr[r] - fr.pix_begin : kPad;
     }
-    if (fr.keys) glob(fr.keys)[o] = key;
+}
+
+// LDS written by some lanes of a wave and read by others: order the wave's accesses
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------- phase: cells
-// One thread per cell: top-3 representatives (Sec. II.5(2)a), local views and
-// consistency (II.5(2)b, Eq. 4-7), joint weight and fusion (Eq. 10-11), output.
+// Top-3 representatives (Sec. II.5(2)a), local views and consistency (II.5(2)b, Eq. 4-7),
+// joint weight and fusion (Eq. 10-11), output.  A wave takes 64 cells at a time through
+// three stages that each keep all 64 lanes busy, handing over through its own LDS stage:
+//   A  four lanes per cell rank the members (each lane every fourth member, lists merged
+//      across the quad), 16 cells at a time;
+//   B  the representatives, compacted, one per lane: back-projection, local views, -ln V;
+//   C  one lane per cell: key, joint weights, fused point, outputs.
+// Waves walk groups of 64 cells; the workgroups of one XCD (dispatched round-robin over
+// the eight) share one contiguous range of cells, so nearby cells, which see nearby
+// pixels, meet in the same L2.
 
 template <int KV, bool LDS_CAMS>
 __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem) {
@@ -1331,129 +1438,254 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
     const DevParams& P = H.prm;
     BatchState* bs = C.bs;
     CellsShared& sh = *reinterpret_cast<CellsShared*>(smem);
-    CamLite* s_cams = reinterpret_cast<CamLite*>(smem + sizeof(CellsShared));
+    const CellsLayout lay = cells_layout(H.n_cams, LDS_CAMS);
+    uint32_t* s_cam_pix = reinterpret_cast<uint32_t*>(smem + lay.cam_pix);
+    CamLite* s_cams = reinterpret_cast<CamLite*>(smem + lay.cams);
     const uint32_t nf = H.n_frames, nc = H.n_cams;
     const bool no_sa = P.flags & 4u, no_mf = P.flags & 1u, no_dc = P.flags & 2u;
     for (uint32_t i = threadIdx.x; i < nc; i += kBlock) {
-        sh.cam_pix[i] = C.camlite[i].pix_off;
+        s_cam_pix[i] = C.camlite[i].pix_off;
         if (LDS_CAMS) s_cams[i] = C.camlite[i];
     }
     for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
         sh.fpix[f] = C.frames[f].pix_begin;
         sh.key_begin[f] = C.fs[f].key_begin;
         sh.cell_begin[f] = no_sa ? C.fs[f].key_begin : C.fs[f].cell_begin;
+        sh.rcount[f] = 0;
     }
     __syncthreads();
     const uint32_t M_tot = n_keys(C);
     const uint32_t S = min(no_sa ? bs->M_tot : bs->S_tot, M_tot);
     const uint32_t n_items = H.n_cell_items;
-    const uint32_t b0 = (uint32_t)(((uint64_t)S * item) / n_items);
-    const uint32_t b1 = (uint32_t)(((uint64_t)S * (item + 1)) / n_items);
-    if (b0 >= b1) return;
     const uint32_t* vals = no_sa ? C.valsA : sorted_vals(C);
     // one source per instantiation, so LDS reads compile to ds_read (a pointer that may be
     // either LDS or global would make every camera read a flat access that waits for all
     // outstanding global loads)
     const CamLite* cams = LDS_CAMS ? s_cams : C.camlite;
-    const CellCtx X{C, cams, sh.cam_pix, vals, (int)nc};
+    const CellCtx X{C, cams, s_cam_pix, vals, (int)nc};
     // confidences in sorted order come from the last radix pass (none ran: gather them)
     const bool have_cs = !no_sa && !no_mf && bs->npass > 0;
     const uint32_t G3 = (uint32_t)(P.G * P.G * P.G);
-    // representatives are counted per frame: the item's first frame in a block reduction,
-    // any other frame directly (items rarely straddle frames)
-    const uint32_t k_first = no_sa ? b0 : min(C.cell_start[b0], M_tot - 1);
-    const int f_item = last_le(sh.fpix, (int)nf, vals[k_first]);
-    uint32_t rsum = 0;
-    for (uint32_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
-        uint32_t start, end;
-        if (no_sa) { start = s; end = s + 1; }
-        else { start = glob(C.cell_start)[s]; end = glob(C.cell_start)[s + 1]; }
-        if (end > M_tot || start >= end) { raise_error(bs, kErrBounds); continue; }
-        Cand rep[3];
-        int nrep = 0;
-        // members in chunks of 8: their confidences are loaded together (one wait per
-        // chunk instead of one per member), then ranked one by one in sorted order
-        for (uint32_t k0 = start; k0 < end; k0 += 8) {
-            float cv[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t k = k0 + j;
-                cv[j] = 1.0f;
-                if (k < end && !no_mf && have_cs) cv[j] = __uint_as_float(glob(C.conf_sorted)[k]);
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t k = k0 + j;
-                if (k >= end) break;
-                Cand c;
-                c.k = k;
-                c.st = 0;
-                c.C = cv[j];
-                if (!no_mf && !have_cs) {
-                    ensure_id(X, c);
-                    const CamLite& cm = cams[c.cam];
-                    c.C = glob(cm.conf)[c.id - cm.pix_off];
+    const bool fr_mids_any = H.any_mids != 0;
+    const uint32_t lane = threadIdx.x & 63u, q = lane & 3u;
+    const uint32_t wpb = kBlock / 64, wave = threadIdx.x >> 6;
+    WaveStage& st = reinterpret_cast<WaveStage*>(smem + lay.stage)[wave];
+    const uint32_t nx = min(8u, n_items), xcd = item % nx, li = item / nx;
+    const uint32_t n_local = (n_items - xcd + nx - 1) / nx;
+    const uint32_t r0 = (uint32_t)((uint64_t)S * xcd / nx);
+    const uint32_t r1 = (uint32_t)((uint64_t)S * (xcd + 1) / nx);
+    for (uint32_t g0 = r0 + (li * wpb + wave) * kStageCells; g0 < r1;
+         g0 += n_local * wpb * kStageCells) {
+        // ---- A: top-3 of 16 cells per pass, four lanes per cell
+        for (uint32_t sub = 0; sub < kStageCells / 16; ++sub) {
+            const uint32_t j = sub * 16u + (lane >> 2);
+            const uint32_t s = g0 + j;
+            uint32_t start = 0, end = 0;
+            bool ok = s < r1;
+            if (ok) {
+                if (no_sa) { start = s; end = s + 1; }
+                else { start = glob(C.cell_start)[s]; end = glob(C.cell_start)[s + 1]; }
+                if (end > M_tot || start >= end) {
+                    if (q == 0) raise_error(bs, kErrBounds);
+                    ok = false;
                 }
-                if (nrep == 3 && !rank_before(X, c, rep[2])) continue;
-                if (nrep < 1 || rank_before(X, c, rep[0])) {
-                    rep[2] = rep[1]; rep[1] = rep[0]; rep[0] = c;
-                } else if (nrep < 2 || rank_before(X, c, rep[1])) {
-                    rep[2] = rep[1]; rep[1] = c;
-                } else {
-                    rep[2] = c;
+            }
+            if (ok) {
+                // this lane's members start + q, start + q + 4, ...: confidences of 8 of
+                // them are loaded together, then ranked by confidence
+                Top3 t;
+                t.C0 = t.C1 = t.C2 = 0.0f;
+                t.k0 = t.k1 = t.k2 = 0;
+                t.n = 0;
+                t.tie = no_mf;                        // all confidences 1: full order
+                if (!no_mf) {
+                    for (uint32_t k0 = start + q; k0 < end; k0 += 32u) {
+                        float cv[8];
+#pragma unroll
+                        for (int jj = 0; jj < 8; ++jj) {
+                            const uint32_t k = k0 + 4u * jj;
+                            cv[jj] = 0.0f;
+                            if (k < end) {
+                                if (have_cs) {
+                                    cv[jj] = __uint_as_float(glob(C.conf_sorted)[k]);
+                                } else {
+                                    const uint32_t id = glob(vals)[k];
+                                    const CamLite& cm = cams[last_le(s_cam_pix, (int)nc, id)];
+                                    cv[jj] = glob(cm.conf)[id - cm.pix_off];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int jj = 0; jj < 8; ++jj) {
+                            const uint32_t k = k0 + 4u * jj;
+                            if (k < end) top3c_insert(t, cv[jj], k);
+                        }
+                    }
                 }
-                if (nrep < 3) ++nrep;
+                top3c_merge<kQuadXor1>(t);
+                top3c_merge<kQuadXor2>(t);
+                const int nrep = (int)min(3u, end - start);
+                uint32_t kr0 = t.k0, kr1 = t.k1, kr2 = t.k2;
+                float cr0 = t.C0, cr1 = t.C1, cr2 = t.C2;
+                if (t.tie) {
+                    // equal confidences among the best: lane 0 ranks the whole cell in the
+                    // full order (confidence, then position, then pixel id)
+                    if (q == 0u) {
+                        Cand rep[3];
+                        int n = 0;
+#pragma unroll 1
+                        for (uint32_t k = start; k < end; ++k) {
+                            Cand c;
+                            c.k = k;
+                            c.st = 0;
+                            c.id = 0;
+                            c.cam = 0;
+                            c.C = 1.0f;
+                            if (!no_mf) {
+                                if (have_cs) {
+                                    c.C = __uint_as_float(glob(C.conf_sorted)[k]);
+                                } else {
+                                    ensure_id(X, c);
+                                    const CamLite& cm = cams[c.cam];
+                                    c.C = glob(cm.conf)[c.id - cm.pix_off];
+                                }
+                            }
+                            top3_insert(X, rep, n, c);
+                        }
+                        kr0 = rep[0].k; cr0 = rep[0].C;
+                        kr1 = n > 1 ? rep[1].k : 0u; cr1 = n > 1 ? rep[1].C : 0.0f;
+                        kr2 = n > 2 ? rep[2].k : 0u; cr2 = n > 2 ? rep[2].C : 0.0f;
+                    }
+                    kr0 = qmov<QuadBcast<0>::ctrl>(kr0);
+                    kr1 = qmov<QuadBcast<0>::ctrl>(kr1);
+                    kr2 = qmov<QuadBcast<0>::ctrl>(kr2);
+                    cr0 = qmovf<QuadBcast<0>::ctrl>(cr0);
+                    cr1 = qmovf<QuadBcast<0>::ctrl>(cr1);
+                    cr2 = qmovf<QuadBcast<0>::ctrl>(cr2);
+                }
+                if ((int)q < nrep) {
+                    st.sid[j * 3 + q] = q == 1u ? kr1 : (q == 2u ? kr2 : kr0);
+                    st.sC[j * 3 + q] = q == 1u ? cr1 : (q == 2u ? cr2 : cr0);
+                }
+                if (fr_mids_any) {
+                    const int f = last_le(sh.fpix, (int)nf, glob(vals)[start]);
+                    const DevFrame& fr = C.frames[f];
+                    if (fr.mids) {
+                        for (uint32_t k = start + q; k < end; k += 4u) {
+                            const uint32_t mo = k - sh.key_begin[f];
+                            if (mo < fr.member_capacity)
+                                glob(fr.mids)[mo] = glob(vals)[k] - fr.pix_begin;
+                        }
+                    }
+                }
+            } else {
+                start = end = 0;
+            }
+            if (q == 0u) {
+                st.start[j] = start;
+                st.end[j] = end;
+                st.bad[j] = 0;
             }
         }
+        wave_sync();
+        // ---- compaction of the representatives (lane = cell)
+        const uint32_t nrep_l = min(3u, st.end[lane] - st.start[lane]);
+        const uint32_t incl = wave_incl(nrep_l);
+        const uint32_t T = __shfl(incl, 63);
+        for (uint32_t r = 0; r < nrep_l; ++r) st.list[incl - nrep_l + r] = (uint8_t)(lane * 3 + r);
+        wave_sync();
+        // ---- B: one representative per lane
+        for (uint32_t i0 = 0; i0 < T; i0 += 64u) {
+            const uint32_t i = i0 + lane;
+            if (i >= T) continue;
+            const uint32_t slot = st.list[i];
+            const uint32_t j = slot / 3u;
+            Cand mine;
+            mine.k = st.sid[slot];
+            mine.C = st.sC[slot];
+            mine.st = 0;
+            mine.id = 0;
+            mine.cam = 0;
+            ensure_id(X, mine);
+            const CamLite& cm = cams[mine.cam];
+            if (mine.id >= H.P_tot || mine.id - cm.pix_off >= (uint32_t)cm.W * (uint32_t)cm.H) {
+                raise_error(bs, kErrBounds);
+                st.bad[j] = 1;
+                continue;
+            }
+            ensure_p(X, mine);
+            const int f = last_le(sh.fpix, (int)nf, mine.id);
+            const DevFrame& fr = C.frames[f];
+            const double expo =
+                no_dc ? 0.0 : neg_log_v<KV>(cams, mine.cam, mine.p, fr.cam_begin, fr.n_cams, P);
+            uint32_t rgb3 = 0;
+            if (fr.rgb != nullptr && fr.has_rgb) {
+                const auto px = glob(cm.rgb + (uint64_t)(mine.id - cm.pix_off) * 3);
+                rgb3 = (uint32_t)px[0] | (uint32_t)px[1] << 8 | (uint32_t)px[2] << 16;
+            }
+            const uint64_t eb = (uint64_t)__double_as_longlong(expo);
+            st.sid[slot] = mine.id;
+            st.px[slot] = mine.p.x;
+            st.py[slot] = mine.p.y;
+            st.pz[slot] = mine.p.z;
+            st.rgb[slot] = rgb3;
+            st.ex_lo[slot] = (uint32_t)eb;
+            st.ex_hi[slot] = (uint32_t)(eb >> 32);
+        }
+        wave_sync();
+        // ---- C: one cell per lane
+        {
+            const uint32_t j = lane, s = g0 + j;
+            const uint32_t start = st.start[j], end = st.end[j];
+            const int nrep = (int)min(3u, end - start);
+            if (nrep > 0 && !st.bad[j]) {
+                float Cr[3];
+                Pt pr[3];
+                double ex[3], wv[3];
+                uint32_t c3[3], ids[3];
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-            if (r < nrep) ensure_id(X, rep[r]);
-        bool bad = false;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            if (r >= nrep) continue;
-            const CamLite& cm = cams[rep[r].cam];
-            if (rep[r].id >= H.P_tot || rep[r].id - cm.pix_off >= (uint32_t)cm.W * (uint32_t)cm.H)
-                bad = true;
-        }
-        if (bad || nrep == 0) { raise_error(bs, kErrBounds); continue; }
-        const int f = last_le(sh.fpix, (int)nf, rep[0].id);
-        const DevFrame& fr = C.frames[f];
-        double expo[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            if (r >= nrep) continue;
-            ensure_p(X, rep[r]);
-            if (!no_dc) expo[r] = neg_log_v<KV>(cams, rep[r].cam, rep[r].p, fr.cam_begin, fr.n_cams, P);
-        }
-        uint64_t key;
-        if (no_sa) {
-            key = rep[0].id - fr.pix_begin;
-        } else {
-            FrameGrid g;
-            frame_grid(C.fs[f], P, g);
-            const CellCoord cc = coarse_cell(g, rep[0].p);
-            const int L = level_of(C.counts[(uint64_t)f * G3 + cc.lin], P);
-            int loc[3];
-            fine_local(cc, L, loc);
-            key = canonical_key(cc, loc, P.Lmax);
-        }
-        const uint32_t o = s - sh.cell_begin[f];
-        if (o < fr.capacity) {
-            emit_cell(cams, fr, o, rep, nrep, expo, end - start, key);
-            if (fr.moff) glob(fr.moff)[o] = start - sh.key_begin[f];
-        }
-        if (fr.mids) {
-            for (uint32_t k = start; k < end; ++k) {
-                const uint32_t mo = k - sh.key_begin[f];
-                if (mo < fr.member_capacity) glob(fr.mids)[mo] = glob(vals)[k] - fr.pix_begin;
+                for (int r = 0; r < 3; ++r) {
+                    const uint32_t sl = j * 3 + r;
+                    const bool h = r < nrep;
+                    Cr[r] = h ? st.sC[sl] : 0.0f;
+                    pr[r] = h ? Pt{st.px[sl], st.py[sl], st.pz[sl]} : Pt{0.0f, 0.0f, 0.0f};
+                    ex[r] = h ? __longlong_as_double((long long)((uint64_t)st.ex_lo[sl] |
+                                                                 ((uint64_t)st.ex_hi[sl] << 32)))
+                              : 0.0;
+                    c3[r] = h ? st.rgb[sl] : 0u;
+                    ids[r] = h ? st.sid[sl] : 0u;
+                    wv[r] = h ? (double)Cr[r] * exp(-ex[r]) : 0.0;
+                }
+                const int f = last_le(sh.fpix, (int)nf, ids[0]);
+                const DevFrame& fr = C.frames[f];
+                const uint32_t o = s - sh.cell_begin[f];
+                if (o < fr.capacity) {
+                    emit_cell(fr, o, nrep, Cr, pr, ex, wv, c3, ids, end - start);
+                    if (fr.moff) glob(fr.moff)[o] = start - sh.key_begin[f];
+                    if (fr.keys) {
+                        uint64_t key;
+                        if (no_sa) {
+                            key = ids[0] - fr.pix_begin;
+                        } else {
+                            FrameGrid g;
+                            frame_grid(C.fs[f], P, g);
+                            const CellCoord cc = coarse_cell(g, pr[0]);
+                            const int L = level_of(C.counts[(uint64_t)f * G3 + cc.lin], P);
+                            int loc[3];
+                            fine_local(cc, L, loc);
+                            key = canonical_key(cc, loc, P.Lmax);
+                        }
+                        glob(fr.keys)[o] = key;
+                    }
+                }
+                atomicAdd(&sh.rcount[f], (uint32_t)nrep);
             }
         }
-        if (f == f_item) rsum += (uint32_t)nrep;
-        else atomicAdd(&C.fs[f].R[item % kRSlots], (uint32_t)nrep);
+        wave_sync();
     }
-    const uint32_t tot = block_sum(rsum, sh.w);
-    if (threadIdx.x == 0 && tot) atomicAdd(&C.fs[f_item].R[item % kRSlots], tot);
+    __syncthreads();
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock)
+        if (sh.rcount[f]) atomicAdd(&C.fs[f].R[item % kRSlots], sh.rcount[f]);
 }
 
 // ---------------------------------------------------------------- phase: final counts
