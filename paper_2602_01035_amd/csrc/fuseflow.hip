@@ -71,21 +71,23 @@ int ilog2(uint32_t v) {
     return r;
 }
 
-size_t down_smem(int items) {
+// scatter staging: keys (u64 worst case) and ids of a tile, per-wave and per-tile digit
+// counters for the configured digit width, the cameras' pixel offsets
+size_t down_smem(int items, int bits, uint32_t ncams) {
     const size_t kt = (size_t)kBlock * items;
-    return kt * 8 + kt * 4 + (4 + 2) * kMaxDigits * 4 + 32 + kMaxBatchCams * 4;
+    return kt * 8 + kt * 4 + (4 + 2) * ((size_t)1 << bits) * 4 + 32 + (size_t)ncams * 4;
 }
 size_t cells_smem(uint32_t ncams) {
     return cells_layout(ncams, ncams <= (uint32_t)kLdsCams).total;
 }
-size_t smem_for(uint32_t kind, int items, uint32_t ncams) {
+size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits) {
     switch (kind) {
         case PH_BACKPROJECT: return 4 * 8 * 4;
         case PH_TILE_REDUCE: return (8 + 32) * 4;
         case PH_HIST: return kHashSlots * 8;
-        case PH_RADIX_UP: return kMaxDigits * 4;
-        case PH_RADIX_DOWN: return down_smem(items);
-        case PH_HEAD_WRITE: return (8 + kMaxFrames) * 4;
+        case PH_RADIX_UP: return ((size_t)1 << bits) * 4;
+        case PH_RADIX_DOWN: return down_smem(items, bits, ncams);
+        case PH_HEAD_WRITE: return kMaxFrames * 8 + 16;
         case PH_CELLS: return cells_smem(ncams);
         case PH_FINAL: return 16;
         default: return 64;
@@ -129,7 +131,7 @@ struct ff_context {
     hipEvent_t last = nullptr;
     bool have_last = false;
     std::vector<void*> allocs;
-    ff_tuning tune{9, 8, 256, 1};
+    ff_tuning tune{8, 8, 256, 1};
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graphs;
     // kernel tracing (events on the call's stream)
@@ -280,6 +282,7 @@ struct Plan {
     std::vector<Launch> launches;
     uint32_t ncams = 0;
     bool wide_views = false;    // K - 1 > 3 kept views
+    int radix_bits = 10;        // widest digit of the sort passes
 };
 
 // Validate one batch and fill the host staging descriptor.  Returns the launch plan and a
@@ -375,6 +378,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     H->lds_cams = ncam <= (uint32_t)kLdsCams ? 1u : 0u;
     plan.ncams = ncam;
     plan.wide_views = prm->k_views > 4;
+    plan.radix_bits = c->tune.radix_bits;
     H->n_px_tiles = ntile;
     H->P_tot = (uint32_t)P;
     const bool no_sa = prm->flags & FF_NO_SA;
@@ -418,8 +422,10 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     add(PH_CELLS, H->n_cell_items, 0);
     add(PH_FINAL, 1, 0);
     char tail[96];
-    std::snprintf(tail, sizeof(tail), "|G%d|L%d|f%u|t%d,%d", G, prm->max_level, prm->flags,
-                  c->tune.radix_bits, c->tune.sort_items);
+    // everything the captured launches depend on besides the per-camera sizes above: grid
+    // and level limits, flags, the per-cell kernel variant, tuning
+    std::snprintf(tail, sizeof(tail), "|G%d|L%d|f%u|w%d|t%d,%d", G, prm->max_level, prm->flags,
+                  plan.wide_views ? 1 : 0, c->tune.radix_bits, c->tune.sort_items);
     shape += tail;
     return FF_OK;
 }
@@ -509,9 +515,21 @@ ff_status probe_mark(ff_context* c, bool begin, hipStream_t s, uint32_t frames,
     return FF_OK;
 }
 
+void launch_cells(const Ctx& C, uint32_t ncams, const Plan& plan, hipStream_t s, dim3 grid,
+                  dim3 block, size_t smem) {
+    const bool lds = ncams <= (uint32_t)kLdsCams;
+    if (plan.wide_views) {
+        if (lds) hipLaunchKernelGGL((k_cells<kMaxK - 1, true>), grid, block, smem, s, C);
+        else hipLaunchKernelGGL((k_cells<kMaxK - 1, false>), grid, block, smem, s, C);
+    } else {
+        if (lds) hipLaunchKernelGGL((k_cells<3, true>), grid, block, smem, s, C);
+        else hipLaunchKernelGGL((k_cells<3, false>), grid, block, smem, s, C);
+    }
+}
+
 template <int ITEMS>
-void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, bool wide_views, hipStream_t s) {
-    const size_t smem = smem_for(L.kind, ITEMS, ncams);
+void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, const Plan& plan, hipStream_t s) {
+    const size_t smem = smem_for(L.kind, ITEMS, ncams, plan.radix_bits);
     const dim3 grid(std::max<uint32_t>(1, L.n)), block(kBlock);
 #define FF_L(K) hipLaunchKernelGGL((k_phase<K, ITEMS>), grid, block, smem, s, C, L.pass)
     switch (L.kind) {
@@ -528,17 +546,7 @@ void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, bool wide_views, 
         case PH_HEAD_COUNT: FF_L(PH_HEAD_COUNT); break;
         case PH_HEAD_SCAN: FF_L(PH_HEAD_SCAN); break;
         case PH_HEAD_WRITE: FF_L(PH_HEAD_WRITE); break;
-        case PH_CELLS: {
-            const bool lds = ncams <= (uint32_t)kLdsCams;
-            if (wide_views) {
-                if (lds) hipLaunchKernelGGL((k_cells<kMaxK - 1, true>), grid, block, smem, s, C);
-                else hipLaunchKernelGGL((k_cells<kMaxK - 1, false>), grid, block, smem, s, C);
-            } else {
-                if (lds) hipLaunchKernelGGL((k_cells<3, true>), grid, block, smem, s, C);
-                else hipLaunchKernelGGL((k_cells<3, false>), grid, block, smem, s, C);
-            }
-            break;
-        }
+        case PH_CELLS: launch_cells(C, ncams, plan, s, grid, block, smem); break;
         case PH_FINAL: FF_L(PH_FINAL); break;
         case PH_CAM_PREP: FF_L(PH_CAM_PREP); break;
         default: break;
@@ -551,7 +559,7 @@ ff_status run_plain(ff_context* c, const Ctx& C, const Plan& plan, hipStream_t s
     const bool tr = c->trace;
     for (const Launch& L : plan.launches) {
         if (tr) { ff_status st = trace_mark(c, trace_slot(L), true, s); if (st != FF_OK) return st; }
-        launch_one<ITEMS>(C, L, plan.ncams, plan.wide_views, s);
+        launch_one<ITEMS>(C, L, plan.ncams, plan, s);
         if (tr) { ff_status st = trace_mark(c, trace_slot(L), false, s); if (st != FF_OK) return st; }
     }
     FF_HIP(hipGetLastError());
@@ -598,6 +606,7 @@ ff_status run_probed(ff_context* c, const Ctx& C, const Plan& plan, const std::s
     Plan seg;
     seg.ncams = plan.ncams;
     seg.wide_views = plan.wide_views;
+    seg.radix_bits = plan.radix_bits;
     int nseg = 0;
     auto flush = [&]() -> ff_status {
         if (seg.launches.empty()) return FF_OK;
@@ -635,8 +644,8 @@ ff_status set_smem_limits() {
             if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) != hipSuccess)
                 result = FF_ERR_HIP;
         };
-        setk((const void*)k_phase<PH_RADIX_DOWN, 8>, down_smem(8));
-        setk((const void*)k_phase<PH_RADIX_DOWN, 16>, down_smem(16));
+        setk((const void*)k_phase<PH_RADIX_DOWN, 8>, down_smem(8, 10, kMaxBatchCams));
+        setk((const void*)k_phase<PH_RADIX_DOWN, 16>, down_smem(16, 10, kMaxBatchCams));
         const size_t cs = std::max(cells_smem((uint32_t)kLdsCams), cells_smem((uint32_t)kMaxBatchCams));
         setk((const void*)k_cells<3, true>, cs);
         setk((const void*)k_cells<3, false>, cs);
@@ -905,7 +914,7 @@ ff_status ff_autotune(ff_context* c, int32_t n_frames, const ff_frame* frames,
     hipEvent_t e0, e1;
     FF_HIP(hipEventCreate(&e0));
     FF_HIP(hipEventCreate(&e1));
-    const int bits[] = {8, 9, 10};
+    const int bits[] = {6, 7, 8, 9, 10};
     const int items[] = {8, 16};
     ff_status st = FF_OK;
     for (int b : bits) {

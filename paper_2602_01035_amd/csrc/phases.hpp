@@ -214,10 +214,10 @@ __device__ __forceinline__ bool project(const Cam& cm, const Pt& p, int& px, int
 template <typename Cam>
 __device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p, float& X, float& Y,
                                              float& Z) {
-    X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
-    Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
     Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
     if (!(Z > 0.0f)) return false;
+    X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
+    Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
     const float rz = __builtin_amdgcn_rcpf(Z);
     const float ta = cm.fx * (X * rz) + cm.cx + 0.5f;
     const float tb = cm.fy * (Y * rz) + cm.cy + 0.5f;
@@ -570,9 +570,9 @@ __device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* sme
 }
 
 // ---------------------------------------------------------------- phase: coarse histogram
-// Sec. II.5(1)c.  Lanes of a wave with the same coarse cell are merged (one ballot per
-// round), the wave leaders accumulate into an LDS hash of the tile's cells, and one global
-// atomic per distinct cell and tile goes out at the end.
+// Sec. II.5(1)c.  Counts are merged per thread (4 neighbouring pixels), then per run of
+// lanes with the same cell (a wave scan), accumulated in an LDS hash of the tile's cells,
+// and one global atomic per distinct cell and tile goes out at the end.
 
 __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
@@ -592,33 +592,37 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t tile, char* smem)
     FrameGrid g;
     frame_grid(C.fs[cm.frame], P, g);
     uint32_t* counts = C.counts + (uint64_t)cm.frame * (uint64_t)(P.G * P.G * P.G);
-    // merge the lanes holding the same cell (one ballot per round); the leader adds the
-    // summed count to the tile's LDS hash (global atomic if the hash is full)
-    auto insert = [&](uint32_t key, uint32_t n, bool has) {
-        uint64_t pending = __ballot(has);
-        while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const uint32_t lk = __shfl(key, leader);
-            const bool peer = has && key == lk;
-            const uint64_t peers = __ballot(peer);
-            const uint32_t tot = wave_sum(peer ? n : 0u);
-            if ((int)lane_id() == leader) {
-                uint32_t h = (lk * 2654435761u) >> (32 - 11);
-                bool done = false;
-                for (int probe = 0; probe < 32 && !done; ++probe) {
-                    const uint32_t old = atomicCAS(&s_key[h], kPad, lk);
-                    if (old == kPad || old == lk) {
-                        atomicAdd(&s_cnt[h], tot);
-                        done = true;
-                    } else {
-                        h = (h + 1) & (kHashSlots - 1);
-                    }
-                }
-                if (!done) atomicAdd(&counts[lk], tot);
+    // add n points of cell `key` to the tile's LDS hash (global atomic if the hash is full)
+    auto hash_add = [&](uint32_t key, uint32_t n) {
+        uint32_t h = (key * 2654435761u) >> (32 - 11);
+        for (int probe = 0; probe < 32; ++probe) {
+            const uint32_t old = atomicCAS(&s_key[h], kPad, key);
+            if (old == kPad || old == key) {
+                atomicAdd(&s_cnt[h], n);
+                return;
             }
-            pending &= ~peers;
-            if (peer) has = false;
+            h = (h + 1) & (kHashSlots - 1);
         }
+        atomicAdd(&counts[key], n);
+    };
+    // consecutive lanes hold consecutive pixels, so equal cells come in runs of lanes: a
+    // wave scan sums each run and only its last lane touches the hash (every lane calls)
+    auto run_add = [&](uint32_t key, uint32_t n) {
+        const uint32_t l = lane_id();
+        const uint32_t kk = n ? key : kPad;            // lanes without points end runs
+        const uint32_t prev = __shfl_up(kk, 1), next = __shfl_down(kk, 1);
+        const bool head = l == 0 || prev != kk;
+        const bool tail = l == 63 || next != kk;
+        const uint32_t incl = wave_incl(n);
+        uint32_t hs = head ? l : 0u;                   // first lane of this lane's run
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(hs, o);
+            if (l >= (uint32_t)o) hs = max(hs, t);
+        }
+        const uint32_t before = __shfl(incl, hs == 0 ? 0 : (int)hs - 1);
+        const uint32_t tot = incl - (hs == 0 ? 0u : before);
+        if (tail && kk != kPad && tot) hash_add(key, tot);
     };
     uint32_t kk[4];
     bool hv[4];
@@ -645,9 +649,10 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t tile, char* smem)
                     hv[q] = false;
                 }
             }
-            insert(k0, n0, n0 > 0);
+            run_add(k0, n0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) insert(kk[q], 1u, hv[q]);
+            for (int q = 0; q < 4; ++q)
+                if (hv[q]) hash_add(kk[q], 1u);
         }
     });
     __syncthreads();
@@ -925,10 +930,11 @@ __device__ void radix_down(const Ctx& C, uint32_t pass, uint32_t tile, char* sme
 
     K* s_key = reinterpret_cast<K*>(smem);                              // [KT]
     uint32_t* s_val = reinterpret_cast<uint32_t*>(s_key + KT);          // [KT]
-    uint32_t* s_wc = s_val + KT;                                        // [4][D] per-wave counts
-    uint32_t* s_doff = s_wc + 4 * kMaxDigits;                           // [D] tile digit offsets
-    uint32_t* s_gb = s_doff + kMaxDigits;                               // [D] global base
-    uint32_t* s_w = s_gb + kMaxDigits;                                  // [8]
+    const uint32_t Dm = 1u << C.hdr->max_radix_bits;                    // widest digit
+    uint32_t* s_wc = s_val + KT;                                        // [4][Dm] per-wave counts
+    uint32_t* s_doff = s_wc + 4 * Dm;                                   // [Dm] tile digit offsets
+    uint32_t* s_gb = s_doff + Dm;                                       // [Dm] global base
+    uint32_t* s_w = s_gb + Dm;                                          // [8]
     uint32_t* s_cam = s_w + 8;                                          // [n_cams] pix_off
     const uint32_t tid = threadIdx.x, w = tid / kWave, l = lane_id();
     const uint32_t nc = C.hdr->n_cams;
@@ -1032,20 +1038,20 @@ __device__ __forceinline__ uint64_t sorted_key(const Ctx& C, uint32_t i) {
 // Cells are runs of equal keys in sorted order: count the run heads per tile, scan, write
 // each cell's first position, and record where each frame's cells begin.
 
+// A sort tile walked wave-striped: wave w takes the tile's w-th quarter, lane l the keys
+// quarter + 64 i + l, so every load of a wave is contiguous.  Bit l of the ballot: key
+// i of lane l starts a run.
 template <int ITEMS>
-__device__ __forceinline__ uint32_t head_mask(const Ctx& C, uint32_t tile, uint32_t n) {
-    const uint32_t t0 = tile * (kBlock * ITEMS) + threadIdx.x * ITEMS;
-    uint32_t m = 0;
-    if (t0 >= n) return 0;
-    uint64_t prev = t0 ? sorted_key(C, t0 - 1) : 0;
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t idx = t0 + i;
-        if (idx >= n) break;
-        const uint64_t k = sorted_key(C, idx);
-        if (idx == 0 || k != prev) m |= 1u << i;
-        prev = k;
-    }
-    return m;
+__device__ __forceinline__ uint32_t head_idx(uint32_t tile, int i) {
+    return tile * (kBlock * ITEMS) + (threadIdx.x >> 6) * (64u * ITEMS) + (uint32_t)i * 64u +
+           lane_id();
+}
+template <int ITEMS>
+__device__ __forceinline__ uint64_t head_ballot(const Ctx& C, uint32_t tile, int i, uint32_t n) {
+    const uint32_t idx = head_idx<ITEMS>(tile, i);
+    bool h = false;
+    if (idx < n) h = idx == 0 || sorted_key(C, idx - 1) != sorted_key(C, idx);
+    return __ballot(h);
 }
 
 template <int ITEMS>
@@ -1053,8 +1059,10 @@ __device__ __forceinline__ void ph_head_count(const Ctx& C, uint32_t tile, char*
     if (C.hdr->prm.flags & 4u) return;
     const uint32_t n = n_keys(C);
     if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
-    const uint32_t c = __popc(head_mask<ITEMS>(C, tile, n));
-    const uint32_t tot = block_sum(c, reinterpret_cast<uint32_t*>(smem));
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) c += (uint32_t)__popcll(head_ballot<ITEMS>(C, tile, i, n));
+    const uint32_t tot = block_sum(lane_id() == 0 ? c : 0u, reinterpret_cast<uint32_t*>(smem));
     if (threadIdx.x == 0) C.head_cnt[tile] = tot;
 }
 
@@ -1078,32 +1086,52 @@ __device__ __forceinline__ void ph_head_scan(const Ctx& C, uint32_t, char* smem)
     }
 }
 
+// frame of a dense key: frames own disjoint ascending key ranges starting at fine_begin
+__device__ __forceinline__ int frame_of_key(const uint64_t* fbeg, int nf, uint64_t k) {
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fbeg[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int ITEMS>
 __device__ __forceinline__ void ph_head_write(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
     if (H.prm.flags & 4u) return;
     const uint32_t n = n_keys(C);
     if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
-    uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);        // [8]
-    uint32_t* s_fpix = s_w + 8;                               // [F]
-    const uint32_t nf = H.n_frames;
-    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) s_fpix[f] = C.frames[f].pix_begin;
-    const uint32_t m = head_mask<ITEMS>(C, tile, n);
-    uint32_t tot;
-    uint32_t o = C.head_cnt[tile] + block_excl(__popc(m), s_w, tot);   // syncs s_fpix too
-    const uint32_t t0 = tile * (kBlock * ITEMS) + threadIdx.x * ITEMS;
-    const uint32_t* vals = sorted_vals(C);
+    uint64_t* s_fbeg = reinterpret_cast<uint64_t*>(smem);               // [F]
+    uint32_t* s_w = reinterpret_cast<uint32_t*>(s_fbeg + kMaxFrames);   // [4]
+    const uint32_t nf = H.n_frames, w = threadIdx.x >> 6, l = lane_id();
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) s_fbeg[f] = C.fs[f].fine_begin;
+    uint64_t m[ITEMS];
+    uint32_t c = 0;
+#pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        if (!(m >> i & 1u)) continue;
-        const uint32_t idx = t0 + i;
-        if (o < C.P_cap) C.cell_start[o] = idx; else raise_error(C.bs, kErrBounds);
-        // the first cell of a frame: its first element follows another frame's element
-        const int f = last_le(s_fpix, (int)nf, vals[idx]);
-        if (idx == 0 || last_le(s_fpix, (int)nf, vals[idx - 1]) != f) {
-            C.fs[f].cell_begin = o;
-            C.fs[f].has_cells = 1;
+        m[i] = head_ballot<ITEMS>(C, tile, i, n);
+        c += (uint32_t)__popcll(m[i]);
+    }
+    if (l == 0) s_w[w] = c;
+    __syncthreads();
+    uint32_t o = C.head_cnt[tile];
+    for (uint32_t v = 0; v < w; ++v) o += s_w[v];
+    const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (m[i] >> l & 1ull) {
+            const uint32_t idx = head_idx<ITEMS>(tile, i);
+            const uint32_t pos = o + (uint32_t)__popcll(m[i] & lt);
+            if (pos < C.P_cap) C.cell_start[pos] = idx; else raise_error(C.bs, kErrBounds);
+            // the first cell of a frame: the previous element belongs to another frame
+            const int f = frame_of_key(s_fbeg, (int)nf, sorted_key(C, idx));
+            if (idx == 0 || frame_of_key(s_fbeg, (int)nf, sorted_key(C, idx - 1)) != f) {
+                C.fs[f].cell_begin = pos;
+                C.fs[f].has_cells = 1;
+            }
         }
-        ++o;
+        o += (uint32_t)__popcll(m[i]);
     }
 }
 
@@ -1206,16 +1234,19 @@ __device__ __forceinline__ bool rank_before(const CellCtx& X, Cand& a, Cand& b) 
 }
 
 // -ln V of representative (cam ri, point p): Eq. 4-7 over the first K-1 views by distance.
-// KV >= K - 1 is the compile-time size of the candidate list.
+// KV >= K - 1 is the compile-time size of the kept list: every camera is tested and the
+// visible ones are inserted into the list sorted by (distance, rank).
 template <int KV>
 __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const Pt& p,
                                             uint32_t fcam0, uint32_t fcams, const DevParams& P) {
     const int keep = (P.K < (int)fcams ? P.K : (int)fcams) - 1;
     if (keep <= 0) return 0.0;
+    int bj[KV];
     float bd[KV];
     uint32_t br[KV];
-    int bj[KV];
     int nb = 0;
+#pragma unroll
+    for (int q = 0; q < KV; ++q) { bj[q] = 0; bd[q] = 0.0f; br[q] = 0; }
     for (uint32_t j = fcam0; j < fcam0 + fcams; ++j) {
         if ((int)j == ri) continue;
         const CamLite& cj = cams[j];
@@ -1223,9 +1254,9 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const P
         if (!in_view_fast(cj, p, X, Y, Z)) continue;
         const float dx = p.x - cj.c[0], dy = p.y - cj.c[1], dz = p.z - cj.c[2];
         const float d2 = (dx * dx + dy * dy) + dz * dz;
-        // insertion into the sorted list of the best `keep` candidates: carry the
-        // candidate down the list, swapping with every entry it ranks before (slots past
-        // nb are free, so whatever is carried into them is discarded)
+        // insertion into the sorted list of the best `keep` candidates: carry the candidate
+        // down the list, swapping with every entry it ranks before (slots past nb are free,
+        // so whatever is carried into them is discarded)
         float cd = d2;
         uint32_t cr = cj.rank;
         int cjx = (int)j;
@@ -1239,8 +1270,8 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const P
         }
         if (nb < keep) ++nb;
     }
-    // exact pixels of the kept views (the camera-frame point is recomputed: it is cheaper
-    // than carrying it through the list), then their depths as independent gathers
+    // pixels of the kept views (the camera-frame point is recomputed: cheaper than carrying
+    // it), then their depths as independent gathers
     int bx[KV], by[KV];
     float dv[KV];
 #pragma unroll

@@ -76,6 +76,17 @@ def test_random_small_rigs(ctx, ff, seed):
     _case(ctx, ff, f, f"random rig {seed} {res}")
 
 
+@pytest.mark.parametrize("n_cams,res", [(9, (160, 120)), (12, (128, 96)), (20, (96, 64))])
+def test_frames_with_many_cameras(ctx, ff, n_cams, res):
+    """More than 8 cameras in a frame: every camera is tested for the local views."""
+    rng = np.random.default_rng(300 + n_cams)
+    cams = ring_cameras([res] * n_cams, jitter_pos=0.3, jitter_target=0.2, rng=rng)
+    prims = _scene_c2(rng, cams)
+    f = make_frame(cams, prims, 9100 + n_cams, outlier_frac=0.03, conf_model="beta")
+    _case(ctx, ff, f, f"{n_cams} cameras {res}", ff.Params(k_views=6))
+    _case(ctx, ff, f, f"{n_cams} cameras {res} batched", ff.Params(k_views=6), batch=True)
+
+
 def test_empty_and_single_pixel(ctx, ff):
     cam = make_camera(37, 5, np.array([0.0, -3, 0]), np.zeros(3))
     D = np.zeros((5, 37), np.float32)

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import core as O
 from tests.conftest import cached_frame
-from tests.gpu_helpers import compare
+from tests.gpu_helpers import compare, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,20 @@ def test_batched_matches_alone_and_oracle(ff, use_graph):
             for k in KEYS:
                 assert np.array_equal(g[k], a[k]), (rep, k)
     compare(outs[0].result(), O.fuse_frame(frames[0]), label="batched vs oracle")
+    ctx.close()
+
+
+def test_graph_replay_follows_view_budget(ff):
+    """The same batch shape with a different K must not replay a graph captured for another
+    per-cell kernel variant."""
+    print("[case] graph replay across k_views", flush=True)
+    frames = [cached_frame("c2")]
+    devs = [ff.to_device(f) for f in frames]
+    ctx = ff.Context(max_pixels=2_000_000, max_cameras=8, max_frames=2)
+    for k in (4, 8, 2, 4):
+        p = ff.Params(k_views=k)
+        g = ctx.fuse_batch(devs, params=p)[0].result()
+        compare(g, O.fuse_frame(frames[0], oracle_params(p)), label=f"k_views={k}")
     ctx.close()
 
 
