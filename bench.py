@@ -63,6 +63,30 @@ def kernel_bytes(name, P, M, S, R, K, kb):
     return 0
 
 
+# Hardware byte counters of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
+# then WRITE_SIZE) over single-frame launches of the 8x1280x720 workload, each scaled by
+# what the same counter reads for a plain copy kernel of known size (1 GiB read, 1 GiB
+# written: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB).  Valid only for the kernel
+# sources they were taken on (their digest); otherwise the traffic is reported as null.
+COUNTERS = {
+    "kernel": "cells_top3_consistency_fuse",
+    "source_digest": "a182219f7386f37b",
+    "fetch_kib_per_frame": 86000.3,
+    "write_kib_per_frame": 52607.7,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("common.hpp", "phases.hpp", "fuseflow.hip"):
+        with open(os.path.join(ROOT, "paper_2602_01035_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def frame_alg_bytes(P, M, S, R, K):
     """Whole-frame algorithmic bytes of the method (three traversals of D and C, one key
     write, one grouping scatter, segmentation/ranking, consistency gathers, output)."""
@@ -248,12 +272,18 @@ def main():
     # processed / its summed duration (HIP events on the lane streams it ran on)
     mean_launch_ms = probe["total_ms"] / max(1, probe["launches"])
     achieved = dom_bytes / (probe["total_ms"] * 1e-3) / 1e9
+    fpl = probe["frames"] / max(1, probe["launches"])
+    traffic = None
+    if COUNTERS["kernel"] == dom and COUNTERS["source_digest"] == kernel_source_digest():
+        per_frame = 1024 * (COUNTERS["fetch_kib_per_frame"] * COUNTERS["fetch_scale"] +
+                            COUNTERS["write_kib_per_frame"] * COUNTERS["write_scale"])
+        traffic = round(per_frame * fpl)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": traffic,
                 "alg_bytes_per_launch": dom_bytes / max(1, probe["launches"]),
                 "mean_launch_ms": round(mean_launch_ms, 5), "launches": probe["launches"],
-                "frames_per_launch": probe["frames"] / max(1, probe["launches"])}
+                "frames_per_launch": fpl}
     B_frame = frame_alg_bytes(P, z["M"], z["S"], z["R"], K)
     B_timed = sum(frame_alg_bytes(P, sizes[k]["M"], sizes[k]["S"], sizes[k]["R"], K)
                   for s in range(args.steps) for k in step_frames(s))

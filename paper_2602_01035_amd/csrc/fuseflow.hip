@@ -188,16 +188,22 @@ ff_status dalloc(ff_context* c, void** p, size_t bytes) {
 }
 
 // All sizes that depend only on the context limits.
+// descriptor: header, frames, cameras, then the camera of every pixel tile (u16)
+size_t tile_cam_offset(int32_t F, int32_t C) {
+    return (sizeof(CallHdr) + sizeof(DevFrame) * (size_t)F + sizeof(DevCam) * (size_t)C + 15) &
+           ~(size_t)15;
+}
+
 struct Sizes {
     uint64_t desc, counts, scan, keys, px_tiles, sort_tiles, cell, dhist;
 };
 Sizes sizes_for(uint64_t P, int32_t C, int32_t F) {
     Sizes s;
-    s.desc = sizeof(CallHdr) + sizeof(DevFrame) * (uint64_t)F + sizeof(DevCam) * (uint64_t)C;
+    s.px_tiles = P / kPxTile + (uint64_t)C + 1;
+    s.desc = tile_cam_offset(F, C) + 2 * s.px_tiles;
     s.counts = (uint64_t)F * 64 * 64 * 64;           // grows on demand for coarse_res > 64
     s.scan = (s.counts + kScanTile - 1) / kScanTile + 1;
     s.keys = P + 1;
-    s.px_tiles = P / kPxTile + (uint64_t)C + 1;
     s.sort_tiles = P / (kBlock * 8) + 2;              // sort tiles hold >= 8 keys per thread
     s.cell = P + 2;
     s.dhist = (uint64_t)kMaxDigits * s.sort_tiles;
@@ -252,6 +258,8 @@ Ctx make_ctx(ff_context* c) {
     C.frames = reinterpret_cast<const DevFrame*>(c->d_desc + sizeof(CallHdr));
     C.cams = reinterpret_cast<DevCam*>(c->d_desc + sizeof(CallHdr) +
                                        sizeof(DevFrame) * (size_t)c->max_frames);
+    C.tile_cam = reinterpret_cast<const uint16_t*>(c->d_desc +
+                                                   tile_cam_offset(c->max_frames, c->max_cams));
     C.bs = c->bs;
     C.fs = c->fs;
     C.tiles = c->tiles;
@@ -282,6 +290,7 @@ struct Plan {
     std::vector<Launch> launches;
     uint32_t ncams = 0;
     bool wide_views = false;    // K - 1 > 3 kept views
+    size_t desc_used = 0;       // bytes of the descriptor this call fills
     int radix_bits = 10;        // widest digit of the sort passes
 };
 
@@ -297,6 +306,9 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     DevFrame* F = reinterpret_cast<DevFrame*>(stage + sizeof(CallHdr));
     DevCam* K = reinterpret_cast<DevCam*>(stage + sizeof(CallHdr) +
                                           sizeof(DevFrame) * (size_t)c->max_frames);
+    const size_t tc_off = tile_cam_offset(c->max_frames, c->max_cams);
+    uint16_t* TC = reinterpret_cast<uint16_t*>(stage + tc_off);
+    const uint64_t tc_cap = (c->desc_bytes - tc_off) / 2;
     std::memset(H, 0, sizeof(CallHdr));
     uint64_t P = 0, tab = 0;
     uint32_t ncam = 0, ntile = 0;
@@ -342,7 +354,10 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
             d.conf = v.conf;
             d.rgb = v.rgb;
             all_rgb = all_rgb && v.rgb;
-            ntile += (uint32_t)((npx + kPxTile - 1) / kPxTile);
+            const uint64_t nt = (npx + kPxTile - 1) / kPxTile;
+            if (ntile + nt > tc_cap) return FF_ERR_INVALID_ARG;    // more pixels than sized for
+            for (uint64_t t = 0; t < nt; ++t) TC[ntile + t] = (uint16_t)ncam;
+            ntile += (uint32_t)nt;
             P += npx;
             fpix += npx;
             ++ncam;
@@ -380,6 +395,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     plan.wide_views = prm->k_views > 4;
     plan.radix_bits = c->tune.radix_bits;
     H->n_px_tiles = ntile;
+    plan.desc_used = tc_off + 2 * (size_t)ntile;
     H->P_tot = (uint32_t)P;
     const bool no_sa = prm->flags & FF_NO_SA;
     const uint64_t ncounts = no_sa ? 0 : (uint64_t)n_frames * G3;
@@ -815,7 +831,7 @@ static ff_status fuse_impl(ff_context* c, int32_t n_frames, const ff_frame* fram
     const Ctx C = make_ctx(c);
     // calls on one context share its workspace: order this one after the previous one
     if (c->have_last) FF_HIP(hipStreamWaitEvent(s, c->last, 0));
-    FF_HIP(hipMemcpyAsync(c->d_desc, c->h_stage[slot], c->desc_bytes, hipMemcpyHostToDevice, s));
+    FF_HIP(hipMemcpyAsync(c->d_desc, c->h_stage[slot], plan.desc_used, hipMemcpyHostToDevice, s));
     FF_HIP(hipEventRecord(c->stage_ev[slot], s));
     const bool graph = batched && c->tune.use_graph && !c->trace;
     if (c->probe_slot >= 0 && !c->trace) {

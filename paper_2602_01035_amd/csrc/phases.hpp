@@ -23,6 +23,7 @@ namespace ff {
 struct Ctx {
     const CallHdr* hdr;
     const DevFrame* frames;
+    const uint16_t* tile_cam;       // camera of every pixel tile
     DevCam* cams;
     BatchState* bs;
     FrameState* fs;
@@ -325,14 +326,9 @@ __device__ __forceinline__ uint64_t canonical_key(const CellCoord& c, const int 
 
 // ---------------------------------------------------------------- lookups
 
-// camera owning pixel tile `tile` (cams sorted by tile_off)
+// camera owning pixel tile `tile` (a table the host writes with the descriptor)
 __device__ __forceinline__ int cam_of_tile(const Ctx& C, uint32_t tile) {
-    int lo = 0, hi = (int)C.hdr->n_cams - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (C.cams[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    return (int)C.tile_cam[tile];
 }
 
 // index of the last entry <= id in an ascending table (camera or frame pixel offsets)
