@@ -165,6 +165,9 @@ def main():
                           kb=4 if int(info[3]) <= 32 else 8)
     d0 = devs[(0, 0)]
     out0 = ff.Output(P, rgb=True)
+    # quality of the fused cloud: Eq. 12 against the frame's own depth maps
+    ctx.fuse(d0["cams"], d0["depth"], d0["conf"], d0["rgb"], out=out0, stream=stream)
+    emc0 = ctx.emc(d0["cams"], d0["depth"], out0, stream=stream)
     ctx.trace(True)
     n_tr = 10
     for _ in range(n_tr):
@@ -332,6 +335,7 @@ def main():
         "speedup_serving_vs_plain": px_srv / px_pl,
         "fused_points_per_s": fused_per_s,
         "frame_sizes": {"P": P, "M": M_mean, "S": S_mean, "R": R_mean},
+        "emc_mm_rig0": round(emc0["emc_m"] * 1e3, 3),
         "latency": latency,
         "kernels": kernels,
         "roofline": roofline,

@@ -65,12 +65,15 @@ typedef enum ff_status {
     FF_ERR_NOT_FOUND = 5      /* server: unknown ticket */
 } ff_status;
 
-/* ff_params.flags: the paper's ablations (Sec. III, Table II) */
+/* ff_params.flags: the paper's ablations (Sec. III, Table II), and the confidence source */
 enum {
     FF_NO_MF = 1u,   /* no measurement confidence: C := 1, gate on depth only */
     FF_NO_DC = 2u,   /* no distance consistency: V := 1 */
-    FF_NO_SA = 4u    /* no spatial-hash aggregation: every gated point is its own output,
+    FF_NO_SA = 4u,   /* no spatial-hash aggregation: every gated point is its own output,
                         in pixel-id order, with V computed per point; keys = pixel ids */
+    FF_CONF_EQ3 = 8u /* the confidence is computed on the device from the depth maps by
+                        Eq. 3 (Sec. II.2) with the paper's weights, as ff_confidence does;
+                        ff_view.conf is ignored and may be NULL */
 };
 
 /* values of *ff_output.status */
@@ -96,7 +99,7 @@ typedef struct ff_params {
     int32_t max_level;            /* deepest refinement level (6) */
     int32_t target_per_cell;      /* refinement target occupancy (16) */
     int32_t level_override;       /* -1, or a level used in every coarse cell */
-    uint32_t flags;               /* FF_NO_MF | FF_NO_DC | FF_NO_SA */
+    uint32_t flags;               /* FF_NO_MF | FF_NO_DC | FF_NO_SA | FF_CONF_EQ3 */
 } ff_params;
 
 typedef struct ff_output {
@@ -206,6 +209,50 @@ typedef struct ff_probe {
 } ff_probe;
 ff_status ff_probe_enable(ff_context* ctx, int32_t slot); /* waits for recorded launches */
 ff_status ff_probe_read(ff_context* ctx, ff_probe* out);  /* waits for recorded launches */
+
+/* ------------------------------------------------------------ measurement confidence
+ * Sec. II.2, Eq. 2-3: C = alpha / (1 + beta G) + gamma / (1 + delta sigma_local), divided
+ * by alpha + gamma so that C lies in (0, 1] as Eq. 2 states (the printed weights alpha =
+ * beta = 0.5, gamma = delta = 1 would span (0, 1.5]).  Readings of what the paper leaves
+ * open: G is the magnitude of the central-difference depth gradient in metres per pixel
+ * (one-sided where only one neighbour along an axis has a valid depth, 0 where none has);
+ * sigma_local is the population standard deviation of the valid depths of the 3x3
+ * window around the pixel; pixels without a valid depth (not finite or <= 0) get 0.
+ * Computed in float32 with one rounding per operation in a fixed order (the gate and the
+ * ranking downstream decide on C exactly). */
+typedef struct ff_conf_params {
+    float alpha, beta, gamma, delta;   /* Eq. 3 weights (paper: 0.5, 0.5, 1, 1) */
+} ff_conf_params;
+void ff_conf_params_default(ff_conf_params* p);
+/* conf_out[k]: device, height*width FP32 written for camera k, from views[k].depth (the
+ * other view fields are not read).  Stream-ordered; no context, nothing allocated.
+ * FF_ERR_INVALID_ARG for null pointers, empty images, >= 2^32 pixels per camera or
+ * non-finite weights. */
+ff_status ff_confidence(int32_t n_cams, const ff_camera* cams, const ff_view* views,
+                        float* const* conf_out, const ff_conf_params* params, void* stream);
+
+/* ------------------------------------------------------------ E_MC evaluator
+ * Sec. III, Eq. 12: E_MC = mean over the points P of a fused cloud of the mean, over the
+ * cameras i that see P, of |z(T_i P) - D_i(pi(T_i P))|.  Readings: a camera sees P when P
+ * is in front of it, its nearest pixel (Eq. 4) is inside the image, the depth there is
+ * valid, and P is not occluded: z <= D + c_occ z^2.  Points seen by no camera are left
+ * out; rho is every `stride`-th point of the cloud.  Decisions in float32 (as the fusion
+ * path projects), error sums in double, summed per workgroup and then in a fixed order
+ * (deterministic). */
+typedef struct ff_emc_params {
+    float c_occ;                  /* occlusion tolerance coefficient, 1/m (0.003) */
+    int32_t stride;               /* evaluate every stride-th point (1) */
+} ff_emc_params;
+void ff_emc_params_default(ff_emc_params* p);
+/* xyz: device [capacity][3] fused points (e.g. ff_output.xyz), count: device number of
+ * points (e.g. ff_output.count, clamped to capacity).  out: device double[3] = {E_MC in
+ * metres, points used, mean number of cameras seeing a used point}.  Uses the context's
+ * descriptor and a partial-sum workspace; ordered after the context's previous calls.
+ * FF_ERR_INVALID_ARG for null pointers, stride < 1, negative c_occ, n_cams outside
+ * 1..max_cameras. */
+ff_status ff_emc(ff_context* ctx, int32_t n_cams, const ff_camera* cams, const ff_view* views,
+                 const float* xyz, const uint32_t* count, uint32_t capacity,
+                 const ff_emc_params* params, double* out, void* stream);
 
 /* ------------------------------------------------------------------------------ serving
  * A streaming loop over several rigs (the paper's per-frame statelessness, Sec. II.1, is

@@ -57,6 +57,7 @@ PAD = np.uint32(0xFFFFFFFF)
 FF_NO_MF = 1   # ablation: no measurement confidence (C := 1, gate on depth only)
 FF_NO_DC = 2   # ablation: no distance consistency (V := 1)
 FF_NO_SA = 4   # ablation: no spatial-hash aggregation (every point is its own cell)
+FF_CONF_EQ3 = 8  # confidence from the depth maps by Eq. 3 (``oracle.measures``), not given
 
 E_MIN, E_MAX = -24, 100   # clamp of the coarse-cell exponent (degenerate extents only)
 
@@ -70,7 +71,7 @@ class Params:
     max_level: int = 6          # deepest refinement level
     target_per_cell: int = 16   # refinement target occupancy
     level_override: int = -1    # >= 0: force this level in every coarse cell
-    flags: int = 0              # FF_NO_MF | FF_NO_DC | FF_NO_SA
+    flags: int = 0              # FF_NO_MF | FF_NO_DC | FF_NO_SA | FF_CONF_EQ3
 
 
 @dataclasses.dataclass
@@ -415,6 +416,8 @@ def validate(params: Params, cams) -> None:
         raise ValueError("sigma must be positive")
     if sum(int(c.width) * int(c.height) for c in cams) >= 2 ** 32:
         raise ValueError("a frame must have fewer than 2^32 pixels")
+    if params.flags & ~(FF_NO_MF | FF_NO_DC | FF_NO_SA | FF_CONF_EQ3):
+        raise ValueError("unknown flag")
 
 
 def fuse(cams_in, depth: Sequence[np.ndarray], conf: Sequence[np.ndarray],
@@ -432,6 +435,10 @@ def fuse(cams_in, depth: Sequence[np.ndarray], conf: Sequence[np.ndarray],
     params = params or Params()
     validate(params, cams_in)
     cams = [camera_f32(c) for c in cams_in]
+    if params.flags & FF_CONF_EQ3:
+        # Sec. II.2: the confidence is computed from the depth maps (Eq. 3), not given
+        from oracle.measures import confidence_eq3
+        conf = [confidence_eq3(d) for d in depth]
     pts = generate_points(cams, depth, conf, params)
     M = len(pts["pix"])
     rgb_pts = _rgb_of_points(rgb, cams, pts["pix"])

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfuseflow.so")
 
 FF_OK, FF_ERR_INVALID_ARG, FF_ERR_OOM, FF_ERR_BUSY, FF_ERR_HIP, FF_ERR_NOT_FOUND = range(6)
-FF_NO_MF, FF_NO_DC, FF_NO_SA = 1, 2, 4
+FF_NO_MF, FF_NO_DC, FF_NO_SA, FF_CONF_EQ3 = 1, 2, 4, 8
 FF_DEV_OK, FF_DEV_OVERFLOW = 0, 1
 PAD = 0xFFFFFFFF
 
@@ -75,6 +75,15 @@ class ff_probe(ctypes.Structure):
                 ("pixels", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
+class ff_conf_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("beta", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("delta", ctypes.c_float)]
+
+
+class ff_emc_params(ctypes.Structure):
+    _fields_ = [("c_occ", ctypes.c_float), ("stride", ctypes.c_int32)]
+
+
 class ff_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("lanes", ctypes.c_int32),
                 ("max_batch_frames", ctypes.c_int32), ("max_cameras", ctypes.c_int32),
@@ -114,6 +123,15 @@ EXPORTS = {
     "ff_trace_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ff_trace_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_trace)]),
     "ff_trace_slot_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ff_conf_params_default": (None, [ctypes.POINTER(ff_conf_params)]),
+    "ff_confidence": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ff_camera),
+                                     ctypes.POINTER(ff_view), ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.POINTER(ff_conf_params), ctypes.c_void_p]),
+    "ff_emc_params_default": (None, [ctypes.POINTER(ff_emc_params)]),
+    "ff_emc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_camera),
+                              ctypes.POINTER(ff_view), ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_uint32, ctypes.POINTER(ff_emc_params), ctypes.c_void_p,
+                              ctypes.c_void_p]),
     "ff_probe_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ff_probe_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_probe)]),
     "ff_server_config_default": (None, [ctypes.POINTER(ff_server_config)]),
@@ -341,8 +359,11 @@ class Context:
     # -- marshalling
     @staticmethod
     def _views(cams, depth, conf, rgb):
+        """ff_camera / ff_view arrays; conf may be None (FF_CONF_EQ3 computes it)."""
         torch = _torch()
         n = len(cams)
+        if conf is None:
+            conf = [None] * n
         if len(depth) != n or len(conf) != n or (rgb is not None and len(rgb) != n):
             raise ValueError("one depth, confidence (and rgb) image per camera")
         ccams = (ff_camera * n)()
@@ -351,9 +372,10 @@ class Context:
             ccams[k] = _camera(cam)
             H, W = int(cam.height), int(cam.width)
             _check_image(depth[k], H, W, torch.float32, f"depth[{k}]")
-            _check_image(conf[k], H, W, torch.float32, f"conf[{k}]")
             views[k].depth = depth[k].data_ptr()
-            views[k].conf = conf[k].data_ptr()
+            if conf[k] is not None:
+                _check_image(conf[k], H, W, torch.float32, f"conf[{k}]")
+                views[k].conf = conf[k].data_ptr()
             if rgb is not None:
                 _check_image(rgb[k], H, W, torch.uint8, f"rgb[{k}]", channels=3)
                 views[k].rgb = rgb[k].data_ptr()
@@ -376,7 +398,7 @@ class Context:
     def _frames(self, frames):
         keep, cf = [], (ff_frame * len(frames))()
         for f, fr in enumerate(frames):
-            ccams, views = self._views(fr["cams"], fr["depth"], fr["conf"], fr.get("rgb"))
+            ccams, views = self._views(fr["cams"], fr["depth"], fr.get("conf"), fr.get("rgb"))
             keep.append((ccams, views))
             cf[f].n_cams = len(fr["cams"])
             cf[f].cams = ctypes.cast(ccams, ctypes.POINTER(ff_camera))
@@ -399,6 +421,22 @@ class Context:
         _check(_lib.ff_fuse_batch(self.h, len(frames), cf, ctypes.byref(prm), co,
                                   _stream_ptr(stream)), "ff_fuse_batch")
         return outs
+
+    def emc(self, cams, depth: Sequence, out: Output, c_occ: float = 0.003, stride: int = 1,
+            stream=None) -> Dict:
+        """Eq. 12 of the fused cloud in `out` against these depth maps (ff_emc); waits for
+        the result: E_MC in metres, points used, mean cameras seeing a used point."""
+        torch = _torch()
+        ccams, views = self._views(cams, depth, None, None)
+        res = torch.zeros(3, dtype=torch.float64, device=out.xyz.device)
+        prm = ff_emc_params()
+        _lib.ff_emc_params_default(ctypes.byref(prm))
+        prm.c_occ, prm.stride = float(c_occ), int(stride)
+        _check(_lib.ff_emc(self.h, len(cams), ccams, views, out.xyz.data_ptr(),
+                           out.count.data_ptr(), out.capacity, ctypes.byref(prm),
+                           res.data_ptr(), _stream_ptr(stream)), "ff_emc")
+        r = res.cpu().tolist()
+        return dict(emc_m=r[0], points=int(round(r[1])), mean_visible=r[2])
 
     def autotune(self, frames: List[Dict], params: Optional[Params] = None,
                  outs: Optional[List[Output]] = None, stream=None) -> Dict:
@@ -501,6 +539,24 @@ class Server:
         return _probe_dict(p)
 
 
+def confidence(cams, depth: Sequence, out: Optional[Sequence] = None, alpha: float = 0.5,
+               beta: float = 0.5, gamma: float = 1.0, delta: float = 1.0,
+               stream=None) -> List:
+    """Eq. 3 confidence maps of the depth maps (ff_confidence), as device tensors."""
+    torch = _torch()
+    n = len(cams)
+    ccams, views = Context._views(cams, depth, None, None)
+    if out is None:
+        out = [torch.empty_like(d) for d in depth]
+    for k, cam in enumerate(cams):
+        _check_image(out[k], int(cam.height), int(cam.width), torch.float32, f"out[{k}]")
+    ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in out])
+    prm = ff_conf_params(alpha, beta, gamma, delta)
+    _check(_lib.ff_confidence(n, ccams, views, ptrs, ctypes.byref(prm), _stream_ptr(stream)),
+           "ff_confidence")
+    return list(out)
+
+
 def to_device(frame, device="cuda", with_rgb=True) -> Dict:
     """Upload a synthetic/host frame (cams, depth, conf, rgb as NumPy) to device tensors."""
     torch = _torch()
@@ -513,4 +569,4 @@ def to_device(frame, device="cuda", with_rgb=True) -> Dict:
 
 
 __all__ = ["Context", "Output", "Params", "Server", "FuseFlowError", "to_device", "version", "lib",
-           "FF_NO_MF", "FF_NO_DC", "FF_NO_SA", "PAD", "EXPORTS"]
+           "FF_NO_MF", "FF_NO_DC", "FF_NO_SA", "FF_CONF_EQ3", "PAD", "EXPORTS", "confidence"]

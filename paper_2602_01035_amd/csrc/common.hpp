@@ -51,6 +51,7 @@ struct DevCam {
     const float* depth;
     const float* conf;
     const uint8_t* rgb;
+    float* conf_out;          // Eq. 3 confidence written here before use (or null)
 };
 
 // the camera fields the per-cell phase needs, staged in LDS there
@@ -132,7 +133,17 @@ enum PhaseKind : uint32_t {
     PH_BACKPROJECT = 0, PH_TILE_REDUCE = 1, PH_HIST = 2, PH_SCAN_A = 3, PH_SCAN_M = 4,
     PH_SCAN_B = 5, PH_KEYS = 6, PH_RADIX_UP = 7, PH_RADIX_SCAN = 8, PH_RADIX_DOWN = 9,
     PH_HEAD_COUNT = 10, PH_HEAD_SCAN = 11, PH_HEAD_WRITE = 12, PH_CELLS = 13, PH_FINAL = 14,
-    PH_CAM_PREP = 15, PH_COUNT = 16
+    PH_CAM_PREP = 15, PH_CONF = 16, PH_COUNT = 17
+};
+
+constexpr int kEmcBlocks = 2048;          // workgroups of the E_MC evaluator
+
+// trace slot of the Eq. 3 confidence phase (the radix passes use 16 .. 30)
+constexpr int kTraceSlotConf = 31;
+
+// weights of Eq. 3
+struct ConfWeights {
+    float a, b, g, d;
 };
 
 }  // namespace ff

@@ -46,6 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(Ctx C, uint32_t pass) {
         case PH_HEAD_WRITE: ph_head_write<ITEMS>(C, item, smem); break;
         case PH_FINAL: ph_final(C, item, smem); break;
         case PH_CAM_PREP: ph_cam_prep(C, item, smem); break;
+        case PH_CONF: ph_conf(C, item, smem); break;
         default: break;
     }
 }
@@ -57,6 +58,72 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KV <= 3 
 void k_cells(Ctx C) {
     extern __shared__ __align__(16) char smem[];
     ph_cells<KV, LDS_CAMS>(C, blockIdx.x, smem);
+}
+
+// Eq. 3 over one depth map, one thread per pixel (the standalone entry point)
+__global__ __launch_bounds__(kBlock) void k_conf_map(const float* D, float* out, int W, int H,
+                                                     ConfWeights w) {
+    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (uint64_t)W * (uint64_t)H) return;
+    const int y = (int)(idx / (uint64_t)W), x = (int)(idx - (uint64_t)y * (uint64_t)W);
+    glob(out)[idx] = conf_eq3(D, W, H, x, y, w);
+}
+
+// Eq. 12, first step: every `stride`-th fused point, grid-stride over kEmcBlocks
+// workgroups; per workgroup the sum of the per-point means, the number of points seen by
+// at least one camera and the sum of their visible-camera counts
+__global__ __launch_bounds__(kBlock) void k_emc(const DevCam* cams, int ncams, const float* xyz,
+                                                const uint32_t* count, uint32_t capacity,
+                                                float c_occ, uint32_t stride, double* part) {
+    __shared__ double s_r[3][kBlock];
+    const uint32_t n = min(*glob(count), capacity);
+    const uint32_t m = (n + stride - 1) / stride;
+    double sum = 0.0, pts = 0.0, vis = 0.0;
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < m; j += gridDim.x * kBlock) {
+        const uint64_t i = (uint64_t)j * stride;
+        const Pt p{glob(xyz)[3 * i], glob(xyz)[3 * i + 1], glob(xyz)[3 * i + 2]};
+        double err;
+        uint32_t cnt;
+        emc_point(cams, ncams, p, c_occ, err, cnt);
+        if (cnt) {
+            sum += err / (double)cnt;
+            pts += 1.0;
+            vis += (double)cnt;
+        }
+    }
+    s_r[0][threadIdx.x] = sum;
+    s_r[1][threadIdx.x] = pts;
+    s_r[2][threadIdx.x] = vis;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) s_r[k][threadIdx.x] += s_r[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = s_r[threadIdx.x][0];
+}
+
+// Eq. 12, second step: fixed-order sum of the partials; out = {E_MC (m), points, mean
+// visible cameras per point}
+__global__ __launch_bounds__(kBlock) void k_emc_final(const double* part, int nblocks,
+                                                      double* out) {
+    __shared__ double s_r[3][kBlock];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+        for (int k = 0; k < 3; ++k) a[k] += part[b * 3 + k];
+    for (int k = 0; k < 3; ++k) s_r[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) s_r[k][threadIdx.x] += s_r[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double pts = s_r[1][0];
+        glob(out)[0] = pts > 0.0 ? s_r[0][0] / pts : 0.0;
+        glob(out)[1] = pts;
+        glob(out)[2] = pts > 0.0 ? s_r[2][0] / pts : 0.0;
+    }
 }
 
 // ============================================================================ host side
@@ -127,6 +194,8 @@ struct ff_context {
     CamLite* camlite = nullptr;
     float* raytab = nullptr;
     uint64_t raytab_cap = 0;
+    float* conf_ws = nullptr;          // Eq. 3 confidence of every pixel (FF_CONF_EQ3)
+    double* emc_part = nullptr;        // per-workgroup partial sums of the E_MC evaluator
     uint64_t sort_tiles_cap = 0;
     hipEvent_t last = nullptr;
     bool have_last = false;
@@ -220,7 +289,7 @@ ff_status validate_params(const ff_params* p) {
     if (p->target_per_cell < 1 || p->k_views < 1 || p->k_views > kMaxK) return FF_ERR_INVALID_ARG;
     if (!(p->sigma > 0.0f) || !std::isfinite(p->sigma)) return FF_ERR_INVALID_ARG;
     if (!std::isfinite(p->tau)) return FF_ERR_INVALID_ARG;
-    if (p->flags & ~7u) return FF_ERR_INVALID_ARG;
+    if (p->flags & ~15u) return FF_ERR_INVALID_ARG;
     return FF_OK;
 }
 
@@ -312,6 +381,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     std::memset(H, 0, sizeof(CallHdr));
     uint64_t P = 0, tab = 0;
     uint32_t ncam = 0, ntile = 0;
+    const bool conf_eq3 = (prm->flags & FF_CONF_EQ3) != 0;
     char buf[64];
     for (int32_t f = 0; f < n_frames; ++f) {
         const ff_frame& fr = frames[f];
@@ -332,7 +402,8 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
         for (int32_t k = 0; k < fr.n_cams; ++k) {
             const ff_camera& cm = fr.cams[k];
             const ff_view& v = fr.views[k];
-            if (cm.width < 1 || cm.height < 1 || !v.depth || !v.conf) return FF_ERR_INVALID_ARG;
+            if (cm.width < 1 || cm.height < 1 || !v.depth || (!v.conf && !conf_eq3))
+                return FF_ERR_INVALID_ARG;
             const uint64_t npx = (uint64_t)cm.width * (uint64_t)cm.height;
             DevCam& d = K[ncam];
             std::memset(&d, 0, sizeof(DevCam));
@@ -346,12 +417,15 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
             d.frame_pix_off = (uint32_t)fpix;
             d.tile_off = ntile;
             d.frame = (uint32_t)f;
-            d.vec_ok = ((uintptr_t)v.depth % 16 == 0 && (uintptr_t)v.conf % 16 == 0) ? 1u : 0u;
+            // with FF_CONF_EQ3 the confidence is computed into the workspace first
+            const float* conf = conf_eq3 ? c->conf_ws + P : v.conf;
+            d.conf_out = conf_eq3 ? c->conf_ws + P : nullptr;
+            d.vec_ok = ((uintptr_t)v.depth % 16 == 0 && (uintptr_t)conf % 16 == 0) ? 1u : 0u;
             d.tab_off = (uint32_t)tab;
             tab += (uint64_t)cm.width + (uint64_t)cm.height;
             if (tab > c->raytab_cap) return FF_ERR_INVALID_ARG;
             d.depth = v.depth;
-            d.conf = v.conf;
+            d.conf = conf;
             d.rgb = v.rgb;
             all_rgb = all_rgb && v.rgb;
             const uint64_t nt = (npx + kPxTile - 1) / kPxTile;
@@ -414,6 +488,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     if (H->npass_max > (uint32_t)kMaxPass) return FF_ERR_INVALID_ARG;
     plan.launches.clear();
     auto add = [&](uint32_t kind, uint32_t n, uint32_t pass) { plan.launches.push_back({kind, n, pass}); };
+    if (conf_eq3) add(PH_CONF, ntile, 0);
     add(PH_CAM_PREP, ncam, 0);
     add(PH_BACKPROJECT, ntile, 0);
     add(PH_TILE_REDUCE, 1, 0);
@@ -447,8 +522,9 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
 }
 
 int trace_slot(const Launch& L) {
+    if (L.kind == PH_CONF) return kTraceSlotConf;
     if (L.kind == PH_RADIX_UP || L.kind == PH_RADIX_SCAN || L.kind == PH_RADIX_DOWN)
-        return std::min(31, 16 + 3 * (int)L.pass + (int)(L.kind - PH_RADIX_UP));
+        return std::min(30, 16 + 3 * (int)L.pass + (int)(L.kind - PH_RADIX_UP));
     return (int)L.kind;
 }
 
@@ -565,6 +641,7 @@ void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, const Plan& plan,
         case PH_CELLS: launch_cells(C, ncams, plan, s, grid, block, smem); break;
         case PH_FINAL: FF_L(PH_FINAL); break;
         case PH_CAM_PREP: FF_L(PH_CAM_PREP); break;
+        case PH_CONF: FF_L(PH_CONF); break;
         default: break;
     }
 #undef FF_L
@@ -708,7 +785,8 @@ uint64_t ff_workspace_bytes(uint64_t max_pixels, int32_t max_cameras, int32_t ma
     return s.desc + sizeof(BatchState) + sizeof(FrameState) * (uint64_t)max_frames +
            s.px_tiles * (sizeof(TilePart) + 4) + s.counts * 12 + s.scan * 8 + 2 * s.keys * 12 +
            s.dhist * 4 + kMaxDigits * 4 + s.sort_tiles * 4 + s.cell * 4 + s.keys * 4 +
-           sizeof(CamLite) * (uint64_t)max_cameras + (max_pixels + max_cameras + 64) * 4 + 4096;
+           sizeof(CamLite) * (uint64_t)max_cameras + (max_pixels + max_cameras + 64) * 4 +
+           (max_pixels + 4) * 4 + (uint64_t)kEmcBlocks * 24 + 4096;
 }
 
 void ff_context_destroy(ff_context* c) {
@@ -782,6 +860,8 @@ ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
     c->raytab_cap = max_pixels + (uint64_t)max_cameras + 64;   // sum of W + H <= P + cameras
     if ((st = dalloc(c, (void**)&c->raytab, c->raytab_cap * 4)) != FF_OK) return fail(st);
     c->sort_tiles_cap = s.sort_tiles;
+    if ((st = dalloc(c, (void**)&c->conf_ws, (max_pixels + 4) * 4)) != FF_OK) return fail(st);
+    if ((st = dalloc(c, (void**)&c->emc_part, (size_t)kEmcBlocks * 3 * 8)) != FF_OK) return fail(st);
     if (set_smem_limits() != FF_OK) return fail(FF_ERR_HIP);
     *out = c;
     return FF_OK;
@@ -863,6 +943,88 @@ ff_status ff_fuse_batch(ff_context* c, int32_t n_frames, const ff_frame* frames,
     return fuse_impl(c, n_frames, frames, params, outs, stream, true);
 }
 
+void ff_conf_params_default(ff_conf_params* p) {
+    if (!p) return;
+    p->alpha = 0.5f;
+    p->beta = 0.5f;
+    p->gamma = 1.0f;
+    p->delta = 1.0f;
+}
+
+ff_status ff_confidence(int32_t n_cams, const ff_camera* cams, const ff_view* views,
+                        float* const* conf_out, const ff_conf_params* prm, void* stream) {
+    if (n_cams < 1 || !cams || !views || !conf_out || !prm) return FF_ERR_INVALID_ARG;
+    if (!std::isfinite(prm->alpha) || !std::isfinite(prm->beta) || !std::isfinite(prm->gamma) ||
+        !std::isfinite(prm->delta) || !(prm->alpha + prm->gamma > 0.0f))
+        return FF_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < n_cams; ++k) {
+        const uint64_t npx = (uint64_t)cams[k].width * (uint64_t)cams[k].height;
+        if (cams[k].width < 1 || cams[k].height < 1 || npx >= 0xFFFFFFFFull || !views[k].depth ||
+            !conf_out[k])
+            return FF_ERR_INVALID_ARG;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const ConfWeights w{prm->alpha, prm->beta, prm->gamma, prm->delta};
+    for (int32_t k = 0; k < n_cams; ++k) {
+        const uint64_t npx = (uint64_t)cams[k].width * (uint64_t)cams[k].height;
+        const dim3 grid((uint32_t)((npx + kBlock - 1) / kBlock)), block(kBlock);
+        hipLaunchKernelGGL(k_conf_map, grid, block, 0, s, views[k].depth, conf_out[k],
+                           cams[k].width, cams[k].height, w);
+    }
+    FF_HIP(hipGetLastError());
+    return FF_OK;
+}
+
+void ff_emc_params_default(ff_emc_params* p) {
+    if (!p) return;
+    p->c_occ = 0.003f;
+    p->stride = 1;
+}
+
+ff_status ff_emc(ff_context* c, int32_t n_cams, const ff_camera* cams, const ff_view* views,
+                 const float* xyz, const uint32_t* count, uint32_t capacity,
+                 const ff_emc_params* prm, double* out, void* stream) {
+    if (!c || n_cams < 1 || n_cams > c->max_cams || !cams || !views || !xyz || !count || !prm ||
+        !out || prm->stride < 1 || !std::isfinite(prm->c_occ) || prm->c_occ < 0.0f)
+        return FF_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < n_cams; ++k)
+        if (cams[k].width < 1 || cams[k].height < 1 || !views[k].depth) return FF_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // camera records in a pinned staging slot that no queued copy still reads
+    const int slot = c->stage;
+    c->stage = (c->stage + 1) % kStageSlots;
+    FF_HIP(hipEventSynchronize(c->stage_ev[slot]));
+    const size_t cam_off = sizeof(CallHdr) + sizeof(DevFrame) * (size_t)c->max_frames;
+    DevCam* K = reinterpret_cast<DevCam*>(c->h_stage[slot] + cam_off);
+    for (int32_t k = 0; k < n_cams; ++k) {
+        DevCam& d = K[k];
+        std::memset(&d, 0, sizeof(DevCam));
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) d.R[i * 3 + j] = cams[k].world_to_cam[i * 4 + j];
+            d.t[i] = cams[k].world_to_cam[i * 4 + 3];
+        }
+        d.fx = cams[k].fx; d.fy = cams[k].fy; d.cx = cams[k].cx; d.cy = cams[k].cy;
+        d.W = cams[k].width; d.H = cams[k].height;
+        d.depth = views[k].depth;
+    }
+    // calls on one context share its descriptor and workspace: order after the previous one
+    if (c->have_last) FF_HIP(hipStreamWaitEvent(s, c->last, 0));
+    FF_HIP(hipMemcpyAsync(c->d_desc + cam_off, c->h_stage[slot] + cam_off,
+                          sizeof(DevCam) * (size_t)n_cams, hipMemcpyHostToDevice, s));
+    FF_HIP(hipEventRecord(c->stage_ev[slot], s));
+    const uint64_t m = ((uint64_t)capacity + (uint64_t)prm->stride - 1) / (uint64_t)prm->stride;
+    const int nb = (int)std::max<uint64_t>(1, std::min<uint64_t>(kEmcBlocks, (m + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_emc, dim3(nb), dim3(kBlock), 0, s,
+                       reinterpret_cast<const DevCam*>(c->d_desc + cam_off), n_cams, xyz, count,
+                       capacity, prm->c_occ, (uint32_t)prm->stride, c->emc_part);
+    hipLaunchKernelGGL(k_emc_final, dim3(1), dim3(kBlock), 0, s, c->emc_part, nb, out);
+    FF_HIP(hipGetLastError());
+    FF_HIP(hipEventRecord(c->last, s));
+    c->have_last = true;
+    return FF_OK;
+}
+
 ff_status ff_trace_enable(ff_context* c, int32_t on) {
     if (!c) return FF_ERR_INVALID_ARG;
     DeviceGuard g(c->device);
@@ -912,8 +1074,8 @@ const char* ff_trace_slot_name(int32_t slot) {
                                   "radix_up_p1", "radix_scan_p1", "radix_down_p1",
                                   "radix_up_p2", "radix_scan_p2", "radix_down_p2",
                                   "radix_up_p3", "radix_scan_p3", "radix_down_p3",
-                                  "radix_up_p4", "radix_scan_p4", "radix_down_p4",
-                                  "radix_pass5+"};
+                                  "radix_up_p4", "radix_scan_p4", "radix_down_p4+",
+                                  "confidence_eq3"};
     if (slot >= 16 && slot < 32) return radix[slot - 16];
     return "unused";
 }

@@ -387,6 +387,109 @@ __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile,
     }
 }
 
+// ---------------------------------------------------------------- Eq. 3 confidence
+// Sec. II.2: C = alpha / (1 + beta G) + gamma / (1 + delta sigma_local), divided by
+// alpha + gamma so that it lies in (0, 1] as Eq. 2 requires.  G: magnitude of the
+// central-difference depth gradient (one-sided where only one neighbour along an axis has
+// a valid depth, 0 where none has); sigma_local: population standard deviation of the
+// valid depths of the 3x3 window.  Pixels without a valid depth get 0.  float32 with one
+// rounding per operation in a fixed order, so the gate and the ranking that use C decide
+// exactly as on any other IEEE machine.
+
+__device__ __forceinline__ bool depth_ok(float d) { return __builtin_isfinite(d) && d > 0.0f; }
+
+__device__ __forceinline__ float conf_eq3(const float* D, int W, int H, int x, int y,
+                                          const ConfWeights& w) {
+    const auto Dg = glob(D);
+    const float d = Dg[(size_t)y * (size_t)W + (size_t)x];
+    if (!depth_ok(d)) return 0.0f;
+    float v[9];
+    bool o[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const float val = in ? Dg[(size_t)yy * (size_t)W + (size_t)xx] : 0.0f;
+        o[k] = in && depth_ok(val);
+        v[k] = o[k] ? val : 0.0f;
+    }
+    // window slots: 1 = (x, y - 1), 3 = (x - 1, y), 5 = (x + 1, y), 7 = (x, y + 1)
+    const float gx = (o[5] && o[3]) ? (v[5] - v[3]) * 0.5f
+                                    : (o[5] ? v[5] - d : (o[3] ? d - v[3] : 0.0f));
+    const float gy = (o[7] && o[1]) ? (v[7] - v[1]) * 0.5f
+                                    : (o[7] ? v[7] - d : (o[1] ? d - v[1] : 0.0f));
+    const float G = sqrtf(gx * gx + gy * gy);
+    float n = 0.0f, s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        if (o[k]) {
+            n = n + 1.0f;
+            s = s + v[k];
+        }
+    }
+    const float mean = s / n;
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        if (o[k]) {
+            const float e = v[k] - mean;
+            acc = acc + e * e;
+        }
+    }
+    const float sd = sqrtf(acc / n);
+    const float t1 = w.a / (1.0f + w.b * G);
+    const float t2 = w.g / (1.0f + w.d * sd);
+    return (t1 + t2) / (w.a + w.g);
+}
+
+// per 4096-pixel tile (the same pixel walk as the other per-pixel phases): C into the
+// camera's conf_out, with the paper's weights
+__device__ __forceinline__ void ph_conf(const Ctx& C, uint32_t tile, char*) {
+    const DevCam& cm = C.cams[cam_of_tile(C, tile)];
+    if (!cm.conf_out) return;
+    const ConfWeights w{0.5f, 0.5f, 1.0f, 1.0f};
+    const uint32_t npx = (uint32_t)cm.W * (uint32_t)cm.H;
+    const uint32_t base = (tile - cm.tile_off) * (uint32_t)kPxTile;
+    const uint32_t W = (uint32_t)cm.W;
+    for (int g = 0; g < kPxPerThread / 4; ++g) {
+        const uint32_t idx0 = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t idx = idx0 + j;
+            if (idx >= npx) break;
+            const uint32_t y = idx / W, x = idx - y * W;
+            glob(cm.conf_out)[idx] = conf_eq3(cm.depth, cm.W, cm.H, (int)x, (int)y, w);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Eq. 12 evaluator
+// Multi-camera depth consistency of one fused point: over the cameras that see it (in
+// front, nearest pixel inside the image, valid depth there, not occluded: z <= D + c z^2)
+// the sum of |z - D| (double) and their number.  Projection as in Eq. 4 (float32, one
+// rounding per operation, the same order as the per-cell phase).
+__device__ __forceinline__ void emc_point(const DevCam* cams, int ncams, const Pt& p, float c_occ,
+                                          double& err, uint32_t& cnt) {
+    err = 0.0;
+    cnt = 0;
+    for (int i = 0; i < ncams; ++i) {
+        const DevCam& cm = cams[i];
+        const float Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
+        if (!(Z > 0.0f)) continue;
+        const float X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
+        const float Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
+        const float u = cm.fx * (X / Z) + cm.cx, v = cm.fy * (Y / Z) + cm.cy;
+        const float fu = floorf(u + 0.5f), fv = floorf(v + 0.5f);
+        if (!(fu >= 0.0f && fu < (float)cm.W && fv >= 0.0f && fv < (float)cm.H)) continue;
+        const float d = glob(cm.depth)[(size_t)fv * (size_t)cm.W + (size_t)fu];
+        if (!depth_ok(d)) continue;
+        const float tol = (c_occ * Z) * Z;
+        if (!(Z <= d + tol)) continue;
+        err += fabs((double)Z - (double)d);
+        ++cnt;
+    }
+}
+
 // ---------------------------------------------------------------- phase: camera prep
 // One workgroup per camera: the centre c = -R^T t (Eq. 8's inverse extrinsics), the rank
 // of the camera in its frame under (centre x, y, z, index) used to break distance ties,

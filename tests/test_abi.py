@@ -23,7 +23,7 @@ def test_header_declares_the_boundary():
     for must in ("ff_context_create", "ff_context_destroy", "ff_params_default", "ff_fuse",
                  "ff_fuse_batch", "ff_status_string", "ff_autotune",
                  "ff_server_create", "ff_server_submit", "ff_server_poll", "ff_server_wait",
-                 "ff_server_stats", "ff_server_destroy"):
+                 "ff_server_stats", "ff_server_destroy", "ff_confidence", "ff_emc"):
         assert must in names, must
 
 
@@ -61,7 +61,8 @@ def test_struct_sizes_match_header():
 
 
 STRUCTS = ("ff_camera", "ff_view", "ff_params", "ff_output", "ff_frame", "ff_tuning",
-           "ff_trace", "ff_probe", "ff_server_config", "ff_stats")
+           "ff_trace", "ff_probe", "ff_server_config", "ff_stats", "ff_conf_params",
+           "ff_emc_params")
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
