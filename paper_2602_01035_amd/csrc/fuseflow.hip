@@ -181,6 +181,7 @@ struct ff_context {
     uint32_t* counts = nullptr;
     uint64_t* fine_base = nullptr;
     uint64_t counts_cap = 0;
+    uint8_t* level = nullptr;
     uint64_t* scan_tile = nullptr;
     void* keysA = nullptr;
     void* keysB = nullptr;
@@ -309,11 +310,13 @@ ff_status grow_counts(ff_context* c, uint64_t need, hipStream_t stream) {
     };
     drop(c->counts);
     drop(c->fine_base);
+    drop(c->level);
     drop(c->scan_tile);
-    c->counts = nullptr; c->fine_base = nullptr; c->scan_tile = nullptr;
+    c->counts = nullptr; c->fine_base = nullptr; c->level = nullptr; c->scan_tile = nullptr;
     ff_status st;
     if ((st = dalloc(c, (void**)&c->counts, need * 4)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->fine_base, need * 8)) != FF_OK) return st;
+    if ((st = dalloc(c, (void**)&c->level, need)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->scan_tile, ((need + kScanTile - 1) / kScanTile + 1) * 8)) != FF_OK)
         return st;
     c->counts_cap = need;
@@ -335,6 +338,7 @@ Ctx make_ctx(ff_context* c) {
     C.tile_off = c->tile_off;
     C.counts = c->counts;
     C.fine_base = c->fine_base;
+    C.level = c->level;
     C.scan_tile = c->scan_tile;
     C.keysA = c->keysA;
     C.keysB = c->keysB;
@@ -493,7 +497,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     add(PH_BACKPROJECT, ntile, 0);
     add(PH_TILE_REDUCE, 1, 0);
     if (!no_sa) {
-        add(PH_HIST, ntile, 0);
+        add(PH_HIST, (ntile + kHistTiles - 1) / kHistTiles, 0);
         add(PH_SCAN_A, H->n_scan_tiles, 0);
         add(PH_SCAN_M, 1, 0);
         add(PH_SCAN_B, H->n_scan_tiles, 0);
@@ -783,7 +787,7 @@ void ff_params_default(ff_params* p) {
 uint64_t ff_workspace_bytes(uint64_t max_pixels, int32_t max_cameras, int32_t max_frames) {
     const Sizes s = sizes_for(max_pixels, max_cameras, max_frames);
     return s.desc + sizeof(BatchState) + sizeof(FrameState) * (uint64_t)max_frames +
-           s.px_tiles * (sizeof(TilePart) + 4) + s.counts * 12 + s.scan * 8 + 2 * s.keys * 12 +
+           s.px_tiles * (sizeof(TilePart) + 4) + s.counts * 13 + s.scan * 8 + 2 * s.keys * 12 +
            s.dhist * 4 + kMaxDigits * 4 + s.sort_tiles * 4 + s.cell * 4 + s.keys * 4 +
            sizeof(CamLite) * (uint64_t)max_cameras + (max_pixels + max_cameras + 64) * 4 +
            (max_pixels + 4) * 4 + (uint64_t)kEmcBlocks * 24 + 4096;
@@ -844,6 +848,7 @@ ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
     if ((st = dalloc(c, (void**)&c->tile_off, 4 * s.px_tiles)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->counts, s.counts * 4)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->fine_base, s.counts * 8)) != FF_OK) return fail(st);
+    if ((st = dalloc(c, (void**)&c->level, s.counts)) != FF_OK) return fail(st);
     c->counts_cap = s.counts;
     if ((st = dalloc(c, (void**)&c->scan_tile, s.scan * 8)) != FF_OK) return fail(st);
     if ((st = dalloc(c, &c->keysA, s.keys * 8)) != FF_OK) return fail(st);

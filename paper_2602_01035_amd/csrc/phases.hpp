@@ -31,6 +31,7 @@ struct Ctx {
     uint32_t* tile_off;      // [n_px_tiles] first compacted position of each pixel tile
     uint32_t* counts;        // [F][G^3] gated points per coarse cell
     uint64_t* fine_base;     // [F][G^3] first dense fine index of each coarse cell
+    uint8_t* level;          // [F][G^3] refinement level of each coarse cell
     uint64_t* scan_tile;     // [n_scan_tiles] tile sums, then exclusive prefixes
     void* keysA;             // sort keys (u32 or u64 by BatchState::key64)
     void* keysB;
@@ -616,21 +617,33 @@ __device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* sme
         const DevFrame& fr = C.frames[f];
         uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
         const uint32_t key_begin = carry;
-        for (uint32_t b = 0; b < fr.n_tiles; b += kBlock) {
-            const uint32_t t = fr.tile_begin + b + tid;
-            const bool in = b + tid < fr.n_tiles;
-            TilePart tp;
-            if (in) tp = C.tiles[t];
-            const uint32_t c = in ? tp.cnt : 0u;
-            if (in && c) {
-                for (int a = 0; a < 3; ++a) {
-                    mn[a] = min(mn[a], tp.mn[a]);
-                    mx[a] = max(mx[a], tp.mx[a]);
+        // 8 consecutive tiles per thread per step: their loads are in flight together
+        constexpr int kPer = 8;
+        for (uint32_t b = 0; b < fr.n_tiles; b += kBlock * kPer) {
+            uint32_t c[kPer], sum = 0;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const uint32_t i = b + tid * kPer + j;
+                const bool in = i < fr.n_tiles;
+                TilePart tp;
+                if (in) tp = C.tiles[fr.tile_begin + i];
+                c[j] = in ? tp.cnt : 0u;
+                if (in && c[j]) {
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = min(mn[a], tp.mn[a]);
+                        mx[a] = max(mx[a], tp.mx[a]);
+                    }
                 }
+                sum += c[j];
             }
             uint32_t tot;
-            const uint32_t ex = block_excl(c, s_w, tot);
-            if (in) C.tile_off[t] = carry + ex;
+            uint32_t run = carry + block_excl(sum, s_w, tot);
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const uint32_t i = b + tid * kPer + j;
+                if (i < fr.n_tiles) C.tile_off[fr.tile_begin + i] = run;
+                run += c[j];
+            }
             carry += tot;
         }
 #pragma unroll
@@ -673,24 +686,15 @@ __device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* sme
 // lanes with the same cell (a wave scan), accumulated in an LDS hash of the tile's cells,
 // and one global atomic per distinct cell and tile goes out at the end.
 
-__device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t tile, char* smem) {
-    const CallHdr& H = *C.hdr;
-    const DevParams& P = H.prm;
-    if (P.flags & 4u) return;
-    uint32_t* s_key = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* s_cnt = s_key + kHashSlots;
-    for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
-        s_key[i] = kPad;
-        s_cnt[i] = 0;
-    }
-    __syncthreads();
-    const DevCam& cm = C.cams[cam_of_tile(C, tile)];
+// one pixel tile into the LDS hash (counts: the frame's, for the rare full-hash case)
+__device__ __forceinline__ void hist_tile(const Ctx& C, const DevCam& cm, uint32_t tile,
+                                          uint32_t* s_key, uint32_t* s_cnt, uint32_t* counts,
+                                          bool no_mf) {
+    const DevParams& P = C.hdr->prm;
     const float* rx = C.raytab + cm.tab_off;
     const float* ry = rx + cm.W;
-    const bool no_mf = P.flags & 1u;
     FrameGrid g;
     frame_grid(C.fs[cm.frame], P, g);
-    uint32_t* counts = C.counts + (uint64_t)cm.frame * (uint64_t)(P.G * P.G * P.G);
     // add n points of cell `key` to the tile's LDS hash (global atomic if the hash is full)
     auto hash_add = [&](uint32_t key, uint32_t n) {
         uint32_t h = (key * 2654435761u) >> (32 - 11);
@@ -754,11 +758,47 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t tile, char* smem)
                 if (hv[q]) hash_add(kk[q], 1u);
         }
     });
-    __syncthreads();
+}
+
+__device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem) {
+    const CallHdr& H = *C.hdr;
+    const DevParams& P = H.prm;
+    if (P.flags & 4u) return;
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* s_cnt = s_key + kHashSlots;
     for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
-        const uint32_t k = s_key[i];
-        if (k != kPad) atomicAdd(&counts[k], s_cnt[i]);
+        s_key[i] = kPad;
+        s_cnt[i] = 0;
     }
+    __syncthreads();
+    const bool no_mf = P.flags & 1u;
+    const uint64_t G3 = (uint64_t)(P.G * P.G * P.G);
+    // this workgroup's tiles share one LDS hash; it goes out to the frame's counts (one
+    // global atomic per distinct cell) when the frame changes and at the end
+    const uint32_t t0 = item * kHistTiles;
+    const uint32_t t1 = min(t0 + (uint32_t)kHistTiles, H.n_px_tiles);
+    if (t0 >= t1) return;
+    uint32_t frame = C.cams[cam_of_tile(C, t0)].frame;
+    auto flush = [&](uint32_t f) {
+        __syncthreads();
+        uint32_t* counts = C.counts + (uint64_t)f * G3;
+        for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
+            const uint32_t k = s_key[i];
+            if (k != kPad) atomicAdd(&counts[k], s_cnt[i]);
+            s_key[i] = kPad;
+            s_cnt[i] = 0;
+        }
+        __syncthreads();
+    };
+    for (uint32_t tile = t0; tile < t1; ++tile) {
+        const DevCam& cm = C.cams[cam_of_tile(C, tile)];
+        if (cm.frame != frame) {
+            flush(frame);
+            frame = cm.frame;
+        }
+        hist_tile(C, cm, tile, s_key, s_cnt, C.counts + (uint64_t)cm.frame * G3, no_mf);
+    }
+    flush(frame);
 }
 
 // ---------------------------------------------------------------- phase: coarse scan
@@ -839,7 +879,10 @@ __device__ __forceinline__ void ph_scan_b(const Ctx& C, uint32_t tile, char* sme
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
         const uint64_t idx = base + i;
-        sp[i] = idx < total ? span_of(C.counts[idx], P) : 0ull;
+        const uint32_t n = idx < total ? C.counts[idx] : 0u;
+        const int L = n ? level_of(n, P) : 0;
+        sp[i] = n ? (1ull << (3 * L)) : 0ull;
+        if (idx < total) C.level[idx] = (uint8_t)L;
         s += sp[i];
     }
     uint64_t tot;
@@ -867,7 +910,7 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
     const bool no_mf = P.flags & 1u;
     const bool no_sa = P.flags & 4u;
     const uint32_t G3 = (uint32_t)(P.G * P.G * P.G);
-    const uint32_t* counts = C.counts + (uint64_t)cm.frame * G3;
+    const uint8_t* lvl = C.level + (uint64_t)cm.frame * G3;
     const uint64_t* fbase = C.fine_base + (uint64_t)cm.frame * G3;
     const bool key64 = bs->key64;
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
@@ -888,7 +931,7 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
         mask |= 1u << k;
         if (no_sa) return;
         const CellCoord cc = coarse_cell(g, p);
-        const int L = level_of(counts[cc.lin], P);
+        const int L = lvl[cc.lin];
         int loc[3];
         fine_local(cc, L, loc);
         kv[k] = fbase[cc.lin] +
@@ -977,9 +1020,7 @@ __device__ __forceinline__ void ph_radix_up(const Ctx& C, uint32_t pass, uint32_
         const uint32_t idx = tile * KT + (uint32_t)i * kBlock + threadIdx.x;
         const bool in = idx < n;
         const uint32_t dg = in ? (uint32_t)(load_key(C, from_b, key64, idx) >> shift) & (D - 1) : 0u;
-        const uint64_t peers = match_peers(dg, in, bits);
-        const uint64_t lt = (lane_id() == 0) ? 0ull : ((~0ull) >> (64 - lane_id()));
-        if (in && (peers & lt) == 0) atomicAdd(&s_h[dg], (uint32_t)__popcll(peers));
+        if (in) atomicAdd(&s_h[dg], 1u);          // a histogram: order does not matter
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < D; d += kBlock) C.digit_hist[(uint64_t)d * nt + tile] = s_h[d];
@@ -995,19 +1036,20 @@ __device__ __forceinline__ void ph_radix_scan(const Ctx& C, uint32_t pass, uint3
     uint32_t* row = C.digit_hist + (uint64_t)d * nt;
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
     uint32_t carry = 0;
-    for (uint32_t b = 0; b < nt; b += kBlock * 4) {
-        uint32_t v[4], loc = 0;
+    constexpr int kPer = 8;                  // consecutive tiles per thread per step
+    for (uint32_t b = 0; b < nt; b += kBlock * kPer) {
+        uint32_t v[kPer], loc = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t i = b + threadIdx.x * 4 + j;
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = b + threadIdx.x * kPer + j;
             v[j] = i < nt ? row[i] : 0u;
             loc += v[j];
         }
         uint32_t tot;
         uint32_t run = carry + block_excl(loc, s_w, tot);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t i = b + threadIdx.x * 4 + j;
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = b + threadIdx.x * kPer + j;
             if (i < nt) row[i] = run;
             run += v[j];
         }
@@ -1171,12 +1213,23 @@ __device__ __forceinline__ void ph_head_scan(const Ctx& C, uint32_t, char* smem)
     const uint32_t n = n_keys(C), nt = n_sort_tiles_real<ITEMS>(C);
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
     uint32_t carry = 0;
-    for (uint32_t b = 0; b < nt; b += kBlock) {
-        const uint32_t i = b + threadIdx.x;
-        const uint32_t v = i < nt ? C.head_cnt[i] : 0u;
+    constexpr int kPer = 8;                  // consecutive tiles per thread per step
+    for (uint32_t b = 0; b < nt; b += kBlock * kPer) {
+        uint32_t v[kPer], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = b + threadIdx.x * kPer + j;
+            v[j] = i < nt ? C.head_cnt[i] : 0u;
+            sum += v[j];
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl(v, s_w, tot);
-        if (i < nt) C.head_cnt[i] = carry + ex;
+        uint32_t run = carry + block_excl(sum, s_w, tot);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = b + threadIdx.x * kPer + j;
+            if (i < nt) C.head_cnt[i] = run;
+            run += v[j];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) {
@@ -1800,7 +1853,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                             FrameGrid g;
                             frame_grid(C.fs[f], P, g);
                             const CellCoord cc = coarse_cell(g, pr[0]);
-                            const int L = level_of(C.counts[(uint64_t)f * G3 + cc.lin], P);
+                            const int L = C.level[(uint64_t)f * G3 + cc.lin];
                             int loc[3];
                             fine_local(cc, L, loc);
                             key = canonical_key(cc, loc, P.Lmax);

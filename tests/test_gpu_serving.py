@@ -184,3 +184,56 @@ def test_server_probe(ff):
     assert p["frames"] == len(devs) and p["launches"] == srv.stats()["batches"]
     assert p["total_ms"] > 0
     srv.close()
+
+
+def test_serving_at_benchmark_scale(ff):
+    """The configuration bench.py times: four 8 x 1280x720 rigs through the serving path
+    (2 lanes, batches of up to 4 frames).  Every frame equals its standalone ff_fuse result
+    bit for bit, and one of them equals the oracle."""
+    print("[case] serving, four 8x1280x720 rigs", flush=True)
+    frames = [cached_frame("c3", rig=r) for r in range(4)]
+    devs = [ff.to_device(f) for f in frames]
+    P = frames[0].pixels
+    ctx = ff.Context(max_pixels=P, max_cameras=8)
+    alone = []
+    for d in devs:
+        alone.append(ctx.fuse(d["cams"], d["depth"], d["conf"], d["rgb"]).result())
+    ctx.close()
+    srv = ff.Server(hbm_budget_bytes=8 << 30, lanes=2, max_batch_frames=4, max_pending=64)
+    outs = [[ff.Output(P, rgb=True) for _ in range(2)] for _ in devs]
+    for rep in range(2):
+        for i, d in enumerate(devs):
+            srv.submit(i, d, outs[i][rep])
+    srv.drain()
+    assert srv.stats()["mean_batch_frames"] > 1.0
+    srv.close()
+    for i in range(len(devs)):
+        for rep in range(2):
+            g = outs[i][rep].result()
+            for k in KEYS:
+                assert np.array_equal(g[k], alone[i][k]), (i, rep, k)
+    compare(outs[2][1].result(), O.fuse_frame(frames[2]), label="c3 rig 2 served")
+
+
+def test_batch_at_frame_limit(ff):
+    """64 frames (the per-batch maximum) of one small camera each, ragged sizes."""
+    print("[case] batch of 64 frames", flush=True)
+    from synth import make_frame, ring_cameras
+    from synth.scenes import _scene_c1
+    rng = np.random.default_rng(64)
+    frames = []
+    for i in range(64):
+        W, H = int(rng.integers(20, 90)), int(rng.integers(10, 60))
+        cams = ring_cameras([(W, H)] * 2, rng=rng, jitter_pos=0.2)
+        frames.append(make_frame(cams[:1 + i % 2], _scene_c1(rng, cams), 6400 + i))
+    devs = [ff.to_device(f) for f in frames]
+    ctx = ff.Context(max_pixels=sum(f.pixels for f in frames), max_cameras=128, max_frames=64)
+    outs = ctx.fuse_batch(devs, members=True)
+    for i in (0, 1, 17, 63):
+        compare(outs[i].result(), O.fuse_frame(frames[i]), label=f"frame {i} of 64")
+    for i, (d, o) in enumerate(zip(devs, outs)):
+        a = ctx.fuse(d["cams"], d["depth"], d["conf"], d["rgb"]).result()
+        g = o.result()
+        for k in KEYS:
+            assert np.array_equal(g[k], a[k]), (i, k)
+    ctx.close()
