@@ -482,8 +482,9 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     const uint32_t KT = (uint32_t)(kBlock * c->tune.sort_items);
     H->sort_items = (uint32_t)c->tune.sort_items;
     H->n_sort_tiles = (uint32_t)std::max<uint64_t>(1, (P + KT - 1) / KT);
-    // per-cell phase: waves walk 16-cell chunks; about 8 workgroups per CU at most
-    H->n_cell_items = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(1, (P + 4095) / 4096));
+    // per-cell phase: waves walk 64-cell steps; at most the workgroups that fit resident
+    // at once (4 per CU at its register use), so no partial second round trails the launch
+    H->n_cell_items = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096));
     H->max_radix_bits = (uint32_t)c->tune.radix_bits;
     // widest possible dense key: frames x coarse cells x 8^Lmax
     const uint32_t bits_max = (uint32_t)(ilog2((uint32_t)n_frames) + 3 * H->prm.log2G +

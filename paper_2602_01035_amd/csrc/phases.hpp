@@ -1659,6 +1659,18 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
     const uint32_t r1 = (uint32_t)((uint64_t)S * (xcd + 1) / nx);
     for (uint32_t g0 = r0 + (li * wpb + wave) * kStageCells; g0 < r1;
          g0 += n_local * wpb * kStageCells) {
+        // member ranges of all 64 cells at once (lane = cell), handed to the quads via LDS
+        {
+            const uint32_t s = g0 + lane;
+            uint32_t a = 0, b = 0;
+            if (s < r1) {
+                if (no_sa) { a = s; b = s + 1; }
+                else { a = glob(C.cell_start)[s]; b = glob(C.cell_start)[s + 1]; }
+            }
+            st.start[lane] = a;
+            st.end[lane] = b;
+        }
+        wave_sync();
         // ---- A: top-3 of 16 cells per pass, four lanes per cell
         for (uint32_t sub = 0; sub < kStageCells / 16; ++sub) {
             const uint32_t j = sub * 16u + (lane >> 2);
@@ -1666,8 +1678,8 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             uint32_t start = 0, end = 0;
             bool ok = s < r1;
             if (ok) {
-                if (no_sa) { start = s; end = s + 1; }
-                else { start = glob(C.cell_start)[s]; end = glob(C.cell_start)[s + 1]; }
+                start = st.start[j];
+                end = st.end[j];
                 if (end > M_tot || start >= end) {
                     if (q == 0) raise_error(bs, kErrBounds);
                     ok = false;
