@@ -360,29 +360,36 @@ __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile,
     const uint32_t npx = (uint32_t)cm.W * (uint32_t)cm.H;
     const uint32_t base = (tile - cm.tile_off) * (uint32_t)kPxTile;
     const uint32_t W = (uint32_t)cm.W;
+    constexpr int NG = kPxPerThread / 4;
+    // every load of the thread first (16 depths and 16 confidences in flight), then the
+    // pixels in order: the work on one group does not wait for the next group's loads
+    float d[NG][4], c[NG][4];
 #pragma unroll
-    for (int g = 0; g < kPxPerThread / 4; ++g) {
+    for (int g = 0; g < NG; ++g) {
         const uint32_t idx = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
-        float d[4], c[4];
         if (cm.vec_ok && idx + 3 < npx) {
             typedef float f4 __attribute__((ext_vector_type(4)));
             const f4 dv = *glob(reinterpret_cast<const f4*>(cm.depth + idx));
             const f4 cv = *glob(reinterpret_cast<const f4*>(cm.conf + idx));
-            d[0] = dv.x; d[1] = dv.y; d[2] = dv.z; d[3] = dv.w;
-            c[0] = cv.x; c[1] = cv.y; c[2] = cv.z; c[3] = cv.w;
+            d[g][0] = dv.x; d[g][1] = dv.y; d[g][2] = dv.z; d[g][3] = dv.w;
+            c[g][0] = cv.x; c[g][1] = cv.y; c[g][2] = cv.z; c[g][3] = cv.w;
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bool in = idx + j < npx;
-                d[j] = in ? glob(cm.depth)[idx + j] : 0.0f;
-                c[j] = in ? glob(cm.conf)[idx + j] : 0.0f;
+                d[g][j] = in ? glob(cm.depth)[idx + j] : 0.0f;
+                c[g][j] = in ? glob(cm.conf)[idx + j] : 0.0f;
             }
         }
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const uint32_t idx = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
         uint32_t y = idx / W;
         uint32_t x = idx - y * W;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            f(g, j, x, y, d[j], c[j], idx + j < npx, idx + j);
+            f(g, j, x, y, d[g][j], c[g][j], idx + j < npx, idx + j);
             if (++x == W) { x = 0; ++y; }
         }
     }
