@@ -71,7 +71,7 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # sources they were taken on (their digest); otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "a0b78ed194038b35",
+    "source_digest": "b378e76233d32cf9",
     "fetch_kib_per_frame": 85374.4,
     "write_kib_per_frame": 54011.8,
     "fetch_scale": 2.0,
@@ -80,11 +80,16 @@ COUNTERS = {
 
 
 def kernel_source_digest():
+    """Digest of the device sources' code (comments and whitespace removed)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("common.hpp", "phases.hpp", "fuseflow.hip"):
-        with open(os.path.join(ROOT, "paper_2602_01035_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2602_01035_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -136,7 +136,8 @@ typedef struct ff_tuning {
     int32_t radix_bits;           /* widest digit of the LSD radix sort, 6..10 (the key bits
                                      are spread evenly over the fewest passes) */
     int32_t sort_items;           /* keys per thread per sort tile: 8 or 16 */
-    int32_t cells_block;          /* threads per block in the per-cell phase: 64..1024 */
+    int32_t cells_block;          /* reserved: the per-cell phase runs 256-thread workgroups
+                                     (read back as 256; any value in 64..1024 is accepted) */
     int32_t use_graph;            /* 1: ff_fuse_batch replays a cached HIP graph (default) */
 } ff_tuning;
 
