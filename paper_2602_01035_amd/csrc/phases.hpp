@@ -1347,7 +1347,8 @@ __device__ __forceinline__ void ensure_p(const CellCtx& X, Cand& a) {
     const uint32_t loc = a.id - cm.pix_off;
     uint32_t x, y;
     pixel_xy(cm, loc, x, y);
-    a.p = backproject_ray(cm, glob(cm.rx)[x], glob(cm.ry)[y], glob(cm.depth)[loc]);
+    a.p = backproject_ray(cm, ((float)x - cm.cx) / cm.fx, ((float)y - cm.cy) / cm.fy,
+                          glob(cm.depth)[loc]);
     a.st = 2;
 }
 
@@ -1424,7 +1425,10 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const P
         const float d = dv[q];
         if (!(__builtin_isfinite(d) && d > 0.0f)) continue;
         const CamLite& cj = cams[bj[q]];
-        const Pt Q = backproject_ray(cj, glob(cj.rx)[bx[q]], glob(cj.ry)[by[q]], d);
+        // the ray of pixel (bx, by) as the quotients the ray tables hold (the same IEEE
+        // operations): two divisions are cheaper here than two more divergent gathers
+        const Pt Q = backproject_ray(cj, ((float)bx[q] - cj.cx) / cj.fx,
+                                     ((float)by[q] - cj.cy) / cj.fy, d);
         const double ex = (double)p.x - (double)Q.x;
         const double ey = (double)p.y - (double)Q.y;
         const double ez = (double)p.z - (double)Q.z;
