@@ -8,7 +8,8 @@ Inputs are synthetic, seeded, and resident in device memory before any timed reg
 A step is one pass of the whole fusion path over one batch of input: one frame from each of
 the 4 rigs (4 x 7,372,800 pixels).  Timed runs:
   * saturation throughput: steps x 4 frames submitted at once to the continuous-batching
-    server (2 lanes, batches of up to 4 frames) -> `value` (input px/s);
+    server (4 lanes, batches of up to 2 frames: the fastest of a sweep over lanes x batch)
+    -> `value` (input px/s);
   * the same frames through the plain loop (one ff_fuse at a time, each waiting for the
     previous to finish);
   * Poisson arrivals at 30 Hz per rig times each --rates multiplier: p50/p99 latency of
@@ -107,8 +108,8 @@ def main():
     ap.add_argument("--frames-per-rig", type=int, default=2)
     ap.add_argument("--rates", default="1,8,12", help="Poisson rate multipliers of 30 Hz/rig")
     ap.add_argument("--trace-seconds", type=float, default=2.0)
-    ap.add_argument("--lanes", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",

@@ -495,7 +495,7 @@ class Server:
 
     def submit(self, rig: int, frame: Dict, out: "Output", params: Optional[Params] = None,
                arrival_s: float = 0.0) -> int:
-        ccams, views = Context._views(frame["cams"], frame["depth"], frame["conf"],
+        ccams, views = Context._views(frame["cams"], frame["depth"], frame.get("conf"),
                                       frame.get("rgb"))
         fr = ff_frame(len(frame["cams"]), ctypes.cast(ccams, ctypes.POINTER(ff_camera)),
                       ctypes.cast(views, ctypes.POINTER(ff_view)))

@@ -138,3 +138,25 @@ def test_bad_arguments(ctx, ff):
         ff.confidence(dev["cams"], dev["depth"], alpha=float("nan"))
     with pytest.raises(ff.FuseFlowError):       # without FF_CONF_EQ3 the confidence is needed
         ctx.fuse(dev["cams"], dev["depth"], None)
+
+
+def test_server_with_device_confidence(ff):
+    """Frames without a confidence map, served with FF_CONF_EQ3, equal the plain call."""
+    print("[case] server with Eq. 3 confidence", flush=True)
+    f = cached_frame("c1")
+    dev = ff.to_device(f)
+    frame = dict(cams=dev["cams"], depth=dev["depth"], rgb=dev["rgb"])
+    p = ff.Params(flags=ff.FF_CONF_EQ3)
+    ctx = ff.Context(max_pixels=f.pixels, max_cameras=4)
+    a = ctx.fuse(dev["cams"], dev["depth"], None, dev["rgb"], params=p).result()
+    ctx.close()
+    srv = ff.Server(hbm_budget_bytes=1 << 30, lanes=2, max_batch_frames=2)
+    outs = [ff.Output(f.pixels, rgb=True) for _ in range(3)]
+    for o in outs:
+        srv.submit(0, frame, o, params=p)
+    srv.drain()
+    srv.close()
+    for o in outs:
+        g = o.result()
+        for k in ("keys", "xyz", "weight", "reps", "n_members", "rgb"):
+            assert np.array_equal(g[k], a[k]), k
