@@ -1685,18 +1685,19 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                 }
             }
             if (ok) {
-                // this lane's members start + q, start + q + 4, ...: confidences of 8 of
-                // them are loaded together, then ranked by confidence
+                // this lane's members start + q, start + q + 4, ...: confidences of 4 of
+                // them are loaded together (most cells give a lane one or two members),
+                // then ranked by confidence
                 Top3 t;
                 t.C0 = t.C1 = t.C2 = 0.0f;
                 t.k0 = t.k1 = t.k2 = 0;
                 t.n = 0;
                 t.tie = no_mf;                        // all confidences 1: full order
                 if (!no_mf) {
-                    for (uint32_t k0 = start + q; k0 < end; k0 += 32u) {
-                        float cv[8];
+                    for (uint32_t k0 = start + q; k0 < end; k0 += 16u) {
+                        float cv[4];
 #pragma unroll
-                        for (int jj = 0; jj < 8; ++jj) {
+                        for (int jj = 0; jj < 4; ++jj) {
                             const uint32_t k = k0 + 4u * jj;
                             cv[jj] = 0.0f;
                             if (k < end) {
@@ -1710,7 +1711,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                             }
                         }
 #pragma unroll
-                        for (int jj = 0; jj < 8; ++jj) {
+                        for (int jj = 0; jj < 4; ++jj) {
                             const uint32_t k = k0 + 4u * jj;
                             if (k < end) top3c_insert(t, cv[jj], k);
                         }
