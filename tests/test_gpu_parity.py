@@ -59,6 +59,7 @@ def test_ablation_flags(ctx, ff, flags):
                                 dict(level_override=0), dict(level_override=6),
                                 dict(coarse_res=16), dict(coarse_res=128, max_level=4),
                                 dict(target_per_cell=1), dict(sigma=0.5, tau=0.8),
+                                dict(sigma=1e-4),      # weights underflow: log-domain mean
                                 dict(coarse_res=1, max_level=10)])
 def test_parameter_variants(ctx, ff, kw):
     _case(ctx, ff, cached_frame("c2"), f"c2 {kw}", ff.Params(**kw))
