@@ -157,7 +157,7 @@ EXPORTS = {
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2602_01035_amd/build.py "
-                          "(or __graft_entry__.build()) first")
+                          "first")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)
