@@ -237,3 +237,20 @@ def test_batch_at_frame_limit(ff):
         for k in KEYS:
             assert np.array_equal(g[k], a[k]), (i, k)
     ctx.close()
+
+
+def test_server_reports_a_failed_frame(ff):
+    """A frame the library rejects (no confidence without FF_CONF_EQ3: refused on the host
+    before any launch) surfaces as an error from drain and from later submits; it does not
+    hang the scheduler."""
+    print("[case] server error path", flush=True)
+    f = cached_frame("c1")
+    dev = ff.to_device(f)
+    srv = ff.Server(hbm_budget_bytes=1 << 30, lanes=2, max_batch_frames=2)
+    srv.submit(0, dict(cams=dev["cams"], depth=dev["depth"]), ff.Output(f.pixels))
+    with pytest.raises(ff.FuseFlowError) as e:
+        srv.drain()
+    assert e.value.status == ff.FF_ERR_INVALID_ARG
+    with pytest.raises(ff.FuseFlowError):
+        srv.submit(0, dev, ff.Output(f.pixels))
+    srv.close()
