@@ -518,3 +518,94 @@ def fuse_frame(frame, params: Optional[Params] = None, debug: bool = False,
     """Convenience wrapper for a ``synth.Frame``-like object."""
     return fuse(frame.cams, frame.depth, frame.conf, frame.rgb if with_rgb else None,
                 params, debug)
+
+
+def sample_cells(n_members: np.ndarray, n_sample: int, seed: int) -> np.ndarray:
+    """Cell indices for a sampled comparison: the first and last cells, the largest cells,
+    cells with one, two and three members, and a seeded uniform draw; sorted, unique."""
+    S = len(n_members)
+    if S == 0:
+        return np.zeros(0, np.int64)
+    rng = np.random.default_rng(seed)
+    pick = [np.array([0, S - 1]), np.argsort(-n_members.astype(np.int64), kind="stable")[:8]]
+    for n in (1, 2, 3):
+        pick.append(np.flatnonzero(n_members == n)[:4])
+    pick.append(rng.choice(S, min(S, n_sample), replace=False))
+    return np.unique(np.concatenate(pick).astype(np.int64))
+
+
+def fuse_sample(cams_in, depth: Sequence[np.ndarray], conf: Sequence[np.ndarray],
+                rgb: Optional[Sequence[np.ndarray]] = None, params: Optional[Params] = None,
+                n_sample: int = 4000, seed: int = 0) -> Dict:
+    """The steps of ``fuse`` with the per-cell work (representatives, views, consistency,
+    fusion: Sec. II.5(2)-(3)) done for a sample of cells only, for frames too large for the
+    whole oracle to finish quickly.
+
+    The partition (Sec. II.5(1)) and grouping are computed for every point, so ``keys``,
+    ``n_members``, ``member_offsets`` and ``member_ids`` cover the whole frame as in
+    ``fuse``; ``cells`` (sorted indices into them) names the sampled cells, and ``xyz``,
+    ``weight``, ``rgb`` and ``reps`` hold the outputs of those cells in that order.  Each
+    sampled cell's outputs are the ones ``fuse`` computes for it: a cell's result depends
+    only on its own members and the depth maps."""
+    params = params or Params()
+    validate(params, cams_in)
+    if params.flags & FF_NO_SA:
+        raise ValueError("fuse_sample covers the aggregated path only")
+    cams = [camera_f32(c) for c in cams_in]
+    if params.flags & FF_CONF_EQ3:
+        from oracle.measures import confidence_eq3
+        conf = [confidence_eq3(d) for d in depth]
+    pts = generate_points(cams, depth, conf, params)
+    M = len(pts["pix"])
+    if M == 0:
+        z = np.zeros(0, np.int64)
+        return dict(keys=np.zeros(0, np.uint64), n_members=np.zeros(0, np.uint32),
+                    member_offsets=np.zeros(1, np.uint32), member_ids=np.zeros(0, np.uint32),
+                    cells=z, xyz=np.zeros((0, 3), F32), weight=np.zeros(0, F32),
+                    rgb=None if rgb is None else np.zeros((0, 3), np.uint8),
+                    reps=np.zeros((0, 3), np.uint32))
+    G = params.coarse_res
+    bmin, bmax = extents(pts["xyz"])                                   # II.5(1)b
+    e = coarse_exponent(bmin, bmax, G)                                 # II.5(1)c
+    q, ci = coarse_cells(pts["xyz"], bmin, e, G)
+    cl = coarse_linear(ci, G)
+    counts = np.bincount(cl, minlength=G ** 3)
+    L = levels(counts, params)[cl]                                     # II.5(1)d
+    keys, _ = cell_keys(q, ci, L, params)                              # II.5(1)e
+    order, ckeys, offsets = group(keys)
+    nmem = np.diff(offsets)
+    cells = sample_cells(nmem, n_sample, seed)
+
+    # the sampled cells' members, regrouped as a smaller partition
+    lens = nmem[cells]
+    sub_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    sub_order = np.concatenate([order[offsets[c]:offsets[c + 1]] for c in cells])
+    keep = np.unique(sub_order)                                        # pixel-id order
+    remap = np.full(M, -1, np.int64)
+    remap[keep] = np.arange(len(keep))
+    spts = {k: v[keep] for k, v in pts.items()}
+    reps, _ = representatives(remap[sub_order], sub_off, spts)         # II.5(2)a
+    flat = reps.reshape(-1)
+    rsel = flat >= 0
+    ridx = flat[rsel]
+    views, px, py = select_views(spts["cam"][ridx], spts["xyz"][ridx], cams,
+                                 params.k_views)                       # II.5(2)b, Eq. 4
+    _, _, expo_r = consistency(spts["cam"][ridx], spts["xyz"][ridx], views, px, py, cams,
+                               depth, params)                          # Eq. 5-7
+    expo = np.zeros(flat.shape)
+    expo[rsel] = expo_r
+    rgb_pts = _rgb_of_points(rgb, cams, spts["pix"])
+    xyz, w, frgb = fuse_cells(reps, expo.reshape(reps.shape), spts, rgb_pts)  # Eq. 10-11
+    rep_pix = np.where(reps >= 0, spts["pix"][np.where(reps >= 0, reps, 0)], -1)
+    return dict(keys=ckeys, n_members=nmem.astype(np.uint32),
+                member_offsets=offsets.astype(np.uint32),
+                member_ids=pts["pix"][order].astype(np.uint32), cells=cells,
+                xyz=xyz, weight=w, rgb=frgb,
+                reps=np.where(rep_pix >= 0, rep_pix, PAD).astype(np.uint32))
+
+
+def fuse_frame_sample(frame, params: Optional[Params] = None, n_sample: int = 4000,
+                      seed: int = 0, with_rgb: bool = True) -> Dict:
+    """``fuse_sample`` for a ``synth.Frame``-like object."""
+    return fuse_sample(frame.cams, frame.depth, frame.conf, frame.rgb if with_rgb else None,
+                       params, n_sample, seed)

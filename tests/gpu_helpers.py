@@ -53,3 +53,24 @@ def compare(g, o, check_members=True, label=""):
         if o.get("rgb") is not None and g.get("rgb") is not None:
             d = np.abs(g["rgb"].astype(int) - o["rgb"].astype(int))
             assert d.max() <= 1, (label, "rgb")
+
+
+def compare_sample(g, s, label=""):
+    """Assert GPU result g == the sampled oracle result s (``O.fuse_sample``): the whole
+    partition bit for bit (count, keys, member counts, membership when g carries it), the
+    per-cell outputs on the sampled cells."""
+    S = len(s["keys"])
+    assert g["status"] == 0, (label, "status", g["status"])
+    assert g["count"] == S, (label, "S", g["count"], S)
+    assert np.array_equal(g["keys"], s["keys"]), (label, "keys")
+    assert np.array_equal(g["n_members"], s["n_members"]), (label, "n_members")
+    if "member_ids" in g:
+        assert np.array_equal(g["member_offsets"], s["member_offsets"]), (label, "offsets")
+        assert np.array_equal(g["member_ids"], s["member_ids"]), (label, "member ids")
+    c = s["cells"]
+    sub = dict(keys=s["keys"][c], n_members=s["n_members"][c], reps=s["reps"], xyz=s["xyz"],
+               weight=s["weight"], rgb=s["rgb"])
+    gs = dict(status=g["status"], count=len(c), keys=g["keys"][c],
+              n_members=g["n_members"][c], reps=g["reps"][c], xyz=g["xyz"][c],
+              weight=g["weight"][c], rgb=None if g.get("rgb") is None else g["rgb"][c])
+    compare(gs, sub, check_members=False, label=label)
