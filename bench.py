@@ -101,6 +101,86 @@ def frame_alg_bytes(P, M, S, R, K):
     return 24 * P + 52 * M + (8 + 4 * (K - 1)) * R + 16 * S
 
 
+MALL_BYTES = 256 << 20
+
+
+def run_regimes(ff, torch, params, stream, args):
+    """Throughput of the two larger workloads, whose inputs per call or step exceed the
+    256 MB last-level cache (one headline frame's 81 MB of inputs fits it):
+      * 16 cameras at mixed resolutions (6 x 640x480, 6 x 1280x720, 4 x 1920x1080), two
+        frames of the moving-sphere sequence per batched call (ff_fuse_batch), with the tile
+        and digit sizes the autotuner picks for that batch;
+      * rigs of 2, 6, 12 and 32 cameras (resolutions drawn from 640x480, 1280x720,
+        1920x1080) through the continuous-batching server at saturation and through the
+        plain loop."""
+    from synth import make_config
+    res = {}
+    t0 = time.time()
+    seq = [ff.to_device(make_config("c4", frame=i)) for i in range(2)]
+    P16 = sum(int(c.width) * int(c.height) for c in seq[0]["cams"])
+    in_bytes = sum(t.numel() * t.element_size() for d in seq
+                   for t in d["depth"] + d["conf"] + d["rgb"])
+    ctx = ff.Context(max_pixels=2 * P16, max_cameras=32, max_frames=2)
+    outs = [ff.Output(P16, rgb=True) for _ in range(2)]
+    tuned = ctx.autotune(seq, params=params, outs=outs, stream=stream)
+    for _ in range(args.warmup):
+        ctx.fuse_batch(seq, params=params, outs=outs, stream=stream)
+    torch.cuda.synchronize()
+    calls = max(4, args.steps // 2)
+    t = time.perf_counter()
+    for _ in range(calls):
+        ctx.fuse_batch(seq, params=params, outs=outs, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ctx.close()
+    res["mixed16_batched"] = {
+        "px_s": 2 * calls * P16 / dt, "ms_per_frame": dt / (2 * calls) * 1e3,
+        "pixels_per_frame": P16, "frames_per_call": 2, "calls": calls, "tuning": tuned,
+        "input_mb_per_call": round(in_bytes / 1e6, 1),
+        "regime": "HBM: inputs exceed the 256 MB last-level cache" if in_bytes > MALL_BYTES
+                  else "inputs fit the 256 MB last-level cache"}
+    del seq
+
+    rigs = [ff.to_device(make_config("c5", rig=r)) for r in range(4)]
+    Pr = [sum(int(c.width) * int(c.height) for c in d["cams"]) for d in rigs]
+    in_bytes = sum(t.numel() * t.element_size() for d in rigs
+                   for t in d["depth"] + d["conf"] + d["rgb"])
+    routs = [[ff.Output(p, rgb=True) for _ in range(2)] for p in Pr]
+    row = {"cameras": [len(d["cams"]) for d in rigs], "pixels_per_frame": Pr,
+           "input_mb_per_step": round(in_bytes / 1e6, 1),
+           "regime": "HBM: inputs exceed the 256 MB last-level cache" if in_bytes > MALL_BYTES
+                     else "inputs fit the 256 MB last-level cache"}
+
+    def run(srv, steps):
+        srv.reset_stats()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in range(steps):
+            for i, d in enumerate(rigs):
+                srv.submit(i, d, routs[i][s % 2], params)
+        srv.drain()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    steps = max(4, args.steps // 2)
+    for name, kw in (("serving", dict(lanes=args.lanes, max_batch_frames=args.batch)),
+                     ("plain", dict(plain=True))):
+        srv = ff.Server(hbm_budget_bytes=24 << 30, max_pending=1 << 20, **kw)
+        run(srv, args.warmup)
+        dt = run(srv, steps)
+        st = srv.stats()
+        row[name] = {"px_s": steps * sum(Pr) / dt, "steps": steps,
+                     "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                     "mean_batch_frames": st["mean_batch_frames"]}
+        srv.close()
+    row["speedup_serving_vs_plain"] = row["serving"]["px_s"] / row["plain"]["px_s"]
+    res["rigs_2_6_12_32_served"] = row
+    log(f"larger workloads in {time.time() - t0:.1f} s: 16 mixed cameras "
+        f"{res['mixed16_batched']['px_s'] / 1e9:.2f} Gpx/s; rigs 2/6/12/32 serving "
+        f"{row['serving']['px_s'] / 1e9:.2f} Gpx/s, plain {row['plain']['px_s'] / 1e9:.2f}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +195,8 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="run a plain copy kernel of this size first (counter scaling)")
+    ap.add_argument("--no-regimes", action="store_true",
+                    help="skip the two larger workloads (16 mixed cameras; 2/6/12/32 rigs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -330,6 +412,31 @@ def main():
         "kernel_ms_per_frame": round(frame_ms_kernels, 4),
     }
 
+    # ------------------------------------------------------------------ copy bandwidth
+    # a plain device copy over 4 GiB (far beyond the 256 MB last-level cache): the HBM rate
+    # a streaming kernel actually reaches, against which the frame fraction is also given
+    ncopy = 1 << 30                                          # float32 elements = 4 GiB
+    ca = torch.empty(ncopy, device="cuda")
+    cb = torch.empty_like(ca)
+    ca.fill_(1.0)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * 4 * ncopy / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
+    torch.cuda.empty_cache()
+    frame_roofline["copy_gbs"] = round(copy_gbs, 1)
+    frame_roofline["frac_serving_vs_copy"] = round(B_timed / dt_srv / (copy_gbs * 1e9), 4)
+    log(f"copy {copy_gbs:.0f} GB/s")
+
+    # ------------------------------------------------------------------ larger workloads
+    regimes = None if args.no_regimes else run_regimes(ff, torch, params, stream, args)
+
     # ------------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -371,6 +478,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "frame_roofline": frame_roofline,
+        "regimes": regimes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
