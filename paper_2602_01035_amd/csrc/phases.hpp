@@ -180,26 +180,30 @@ __device__ __forceinline__ bool finite3(const Pt& p) {
 // nearest pixel floor(u + 1/2), floor(v + 1/2) of u = fx X/Z + cx, v = fy Y/Z + cy inside
 // the image.  The division is done only where it matters: an approximate reciprocal decides
 // points clearly inside or outside (the 1/16 px margin dwarfs its error, < 0.03 px for
-// |u| < 1e5), and the exact IEEE quotients decide points near a border.  X, Y, Z are
-// returned for the caller.
+// |u| < 1e5; beyond that the point is outside by far more than its relative error), and
+// the exact IEEE quotients decide points near a border.  "Clearly outside" is a
+// disjunction of ordered comparisons, so an approximation that is not a number (0 times
+// the infinite reciprocal of a subnormal Z) is never clearly anything and goes to the exact
+// quotients.  Written without early exits: only the rare border case branches.
 template <typename Cam>
-__device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p, float& X, float& Y,
-                                             float& Z) {
-    Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
-    if (!(Z > 0.0f)) return false;
-    X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
-    Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
+__device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p) {
+    const float Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
+    const float X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
+    const float Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
     const float rz = __builtin_amdgcn_rcpf(Z);
     const float ta = cm.fx * (X * rz) + cm.cx + 0.5f;
     const float tb = cm.fy * (Y * rz) + cm.cy + 0.5f;
     const float W = (float)cm.W, H = (float)cm.H, m = 0.0625f;
-    const bool sure_in = ta >= m && ta < W - m && tb >= m && tb < H - m;
-    const bool sure_out = !(ta >= -m && ta < W + m && tb >= -m && tb < H + m);
-    if (sure_in) return true;
-    if (sure_out) return false;
-    const float u = cm.fx * (X / Z) + cm.cx, v = cm.fy * (Y / Z) + cm.cy;
-    const float fu = floorf(u + 0.5f), fv = floorf(v + 0.5f);
-    return (fu >= 0.0f) && (fu < W) && (fv >= 0.0f) && (fv < H);
+    const bool front = Z > 0.0f;
+    const bool sure_in = (ta >= m) & (ta < W - m) & (tb >= m) & (tb < H - m);
+    const bool sure_out = (ta < -m) | (ta >= W + m) | (tb < -m) | (tb >= H + m);
+    bool in = front & sure_in;
+    if (front & !sure_in & !sure_out) {
+        const float u = cm.fx * (X / Z) + cm.cx, v = cm.fy * (Y / Z) + cm.cy;
+        const float fu = floorf(u + 0.5f), fv = floorf(v + 0.5f);
+        in = (fu >= 0.0f) && (fu < W) && (fv >= 0.0f) && (fv < H);
+    }
+    return in;
 }
 
 // exact nearest pixel of a point known to be in view (the arithmetic of the exact branch
@@ -1382,41 +1386,41 @@ __device__ __forceinline__ bool rank_before(const CellCtx& X, Cand& a, Cand& b) 
 }
 
 // -ln V of representative (cam ri, point p): Eq. 4-7 over the first K-1 views by distance.
-// KV >= K - 1 is the compile-time size of the kept list: every camera is tested and the
-// visible ones are inserted into the list sorted by (distance, rank).
+// KV >= K - 1 is the compile-time size of the kept list.  Every camera of the frame is
+// tested; a visible one becomes the 64-bit key (bits of the squared distance, camera rank,
+// camera index).  The bits of a non-negative float order like its value and ranks are
+// unique within a frame, so keys order candidates by (distance, rank).  A branch-free
+// insertion keeps the KV smallest keys sorted (an empty slot holds the largest key).
 template <int KV>
 __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const Pt& p,
                                             uint32_t fcam0, uint32_t fcams, const DevParams& P) {
     const int keep = (P.K < (int)fcams ? P.K : (int)fcams) - 1;
     if (keep <= 0) return 0.0;
-    int bj[KV];
-    float bd[KV];
-    uint32_t br[KV];
-    int nb = 0;
+    constexpr uint64_t kNone = ~0ull;
+    uint64_t best[KV];
 #pragma unroll
-    for (int q = 0; q < KV; ++q) { bj[q] = 0; bd[q] = 0.0f; br[q] = 0; }
+    for (int q = 0; q < KV; ++q) best[q] = kNone;
     for (uint32_t j = fcam0; j < fcam0 + fcams; ++j) {
-        if ((int)j == ri) continue;
         const CamLite& cj = cams[j];
-        float X, Y, Z;
-        if (!in_view_fast(cj, p, X, Y, Z)) continue;
+        const bool vis = in_view_fast(cj, p) & ((int)j != ri);
         const float dx = p.x - cj.c[0], dy = p.y - cj.c[1], dz = p.z - cj.c[2];
         const float d2 = (dx * dx + dy * dy) + dz * dz;
-        // insertion into the sorted list of the best `keep` candidates: carry the candidate
-        // down the list, swapping with every entry it ranks before (slots past nb are free,
-        // so whatever is carried into them is discarded)
-        float cd = d2;
-        uint32_t cr = cj.rank;
-        int cjx = (int)j;
+        uint64_t c = vis ? ((uint64_t)__float_as_uint(d2) << 32 | (uint64_t)cj.rank << 16 | j)
+                         : kNone;
 #pragma unroll
         for (int q = 0; q < KV; ++q) {
-            if (q < keep && (q >= nb || cd < bd[q] || (cd == bd[q] && cr < br[q]))) {
-                const float t = bd[q]; bd[q] = cd; cd = t;
-                const uint32_t tr = br[q]; br[q] = cr; cr = tr;
-                const int tj = bj[q]; bj[q] = cjx; cjx = tj;
-            }
+            const bool lt = c < best[q];
+            const uint64_t lo = lt ? c : best[q];
+            c = lt ? best[q] : c;
+            best[q] = lo;
         }
-        if (nb < keep) ++nb;
+    }
+    int nb = 0;
+    int bj[KV];
+#pragma unroll
+    for (int q = 0; q < KV; ++q) {
+        bj[q] = (int)(best[q] & 0xFFFFu);
+        if (q < keep && best[q] != kNone) nb = q + 1;
     }
     // pixels of the kept views (the camera-frame point is recomputed: cheaper than carrying
     // it), then their depths as independent gathers
