@@ -79,8 +79,12 @@ enum {
 /* values of *ff_output.status */
 enum { FF_DEV_OK = 0, FF_DEV_OVERFLOW = 1 };
 
+/* Fusion calls reject (FF_ERR_INVALID_ARG) a camera with a non-finite parameter, a side
+ * above 16384 px, a principal point beyond +-16384 px or a focal length outside
+ * [2^-20, 2^20] px in magnitude: the range in which the per-cell kernel's approximate
+ * field-of-view pre-test is proven to take the exact float32 decisions. */
 typedef struct ff_camera {
-    int32_t width, height;        /* pixels */
+    int32_t width, height;        /* pixels, 1..16384 */
     float fx, fy, cx, cy;         /* intrinsics K (pixel units) */
     float world_to_cam[12];       /* [R | t] row-major 3x4: X_cam = R X_world + t */
 } ff_camera;

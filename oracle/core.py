@@ -399,6 +399,22 @@ def _rgb_of_points(frame_rgb, cams, pix):
     return flat[pix]
 
 
+def validate_camera(cam) -> None:
+    """The camera range the library accepts: finite parameters, sides 1..16384 px,
+    principal point within +-16384 px, focal lengths 2^-20 <= |f| <= 2^20 px."""
+    f = [float(np.float32(v)) for v in (cam.fx, cam.fy)]
+    c = [float(np.float32(v)) for v in (cam.cx, cam.cy)]
+    T = np.asarray(cam.world_to_cam, np.float32)
+    if not (1 <= int(cam.width) <= 16384 and 1 <= int(cam.height) <= 16384):
+        raise ValueError("image sides must be 1..16384")
+    if not all(math.isfinite(v) and 2.0 ** -20 <= abs(v) <= 2.0 ** 20 for v in f):
+        raise ValueError("focal lengths must be finite with 2^-20 <= |f| <= 2^20")
+    if not all(math.isfinite(v) and abs(v) <= 16384.0 for v in c):
+        raise ValueError("principal point must be finite and within +-16384")
+    if not np.all(np.isfinite(T)):
+        raise ValueError("extrinsics must be finite")
+
+
 def validate(params: Params, cams) -> None:
     """Reject parameter sets the key layout or the method cannot represent."""
     G = params.coarse_res
@@ -416,6 +432,8 @@ def validate(params: Params, cams) -> None:
         raise ValueError("sigma must be positive")
     if sum(int(c.width) * int(c.height) for c in cams) >= 2 ** 32:
         raise ValueError("a frame must have fewer than 2^32 pixels")
+    for c in cams:
+        validate_camera(c)
     if params.flags & ~(FF_NO_MF | FF_NO_DC | FF_NO_SA | FF_CONF_EQ3):
         raise ValueError("unknown flag")
 

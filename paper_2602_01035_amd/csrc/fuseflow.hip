@@ -281,6 +281,21 @@ Sizes sizes_for(uint64_t P, int32_t C, int32_t F) {
     return s;
 }
 
+// Camera parameters for which the per-cell kernel's approximate field-of-view pre-test is
+// proven to take the exact decisions: all finite, image sides and principal point within
+// 2^14 px, focal lengths 2^-20 <= |f| <= 2^20 px.
+bool camera_ok(const ff_camera& cm) {
+    if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384) return false;
+    for (float f : {cm.fx, cm.fy})
+        if (!std::isfinite(f) || !(std::fabs(f) >= 0x1p-20f && std::fabs(f) <= 0x1p20f))
+            return false;
+    for (float c : {cm.cx, cm.cy})
+        if (!std::isfinite(c) || std::fabs(c) > 16384.0f) return false;
+    for (float v : cm.world_to_cam)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
 ff_status validate_params(const ff_params* p) {
     if (!p) return FF_ERR_INVALID_ARG;
     const int G = p->coarse_res;
@@ -407,8 +422,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
         for (int32_t k = 0; k < fr.n_cams; ++k) {
             const ff_camera& cm = fr.cams[k];
             const ff_view& v = fr.views[k];
-            if (cm.width < 1 || cm.height < 1 || !v.depth || (!v.conf && !conf_eq3))
-                return FF_ERR_INVALID_ARG;
+            if (!camera_ok(cm) || !v.depth || (!v.conf && !conf_eq3)) return FF_ERR_INVALID_ARG;
             const uint64_t npx = (uint64_t)cm.width * (uint64_t)cm.height;
             DevCam& d = K[ncam];
             std::memset(&d, 0, sizeof(DevCam));

@@ -179,9 +179,11 @@ __device__ __forceinline__ bool finite3(const Pt& p) {
 // Eq. 4 field-of-view decision: camera-frame point X = R p + t, in front (Z > 0), and the
 // nearest pixel floor(u + 1/2), floor(v + 1/2) of u = fx X/Z + cx, v = fy Y/Z + cy inside
 // the image.  The division is done only where it matters: an approximate reciprocal decides
-// points clearly inside or outside (the 1/16 px margin dwarfs its error, < 0.03 px for
-// |u| < 1e5; beyond that the point is outside by far more than its relative error), and
-// the exact IEEE quotients decide points near a border.  "Clearly outside" is a
+// points clearly inside or outside, and the exact IEEE quotients decide points near a
+// border.  The approximate u + 1/2 differs from the exact one by at most 3.6e-7 |fx X/Z|
+// plus two half-ulps of the sums; with the camera range the boundary admits (sides and
+// principal point within 2^14 px) that is < 0.04 px wherever |u| < 2^16, inside the 1/16 px
+// margin, and beyond 2^16 the point is outside by far more than the error.  "Clearly outside" is a
 // disjunction of ordered comparisons, so an approximation that is not a number (0 times
 // the infinite reciprocal of a subnormal Z) is never clearly anything and goes to the exact
 // quotients.  Written without early exits: only the rare border case branches.

@@ -202,3 +202,8 @@ def test_bad_arguments_raise(ctx, ff):
     with pytest.raises(ff.FuseFlowError):
         small.fuse(dev["cams"], dev["depth"], dev["conf"])
     small.close()
+    # cameras outside the admitted range (the oracle rejects the same ones)
+    from tests.test_oracle_pins import _bad_cameras
+    for bad in _bad_cameras(dev["cams"][0]):
+        with pytest.raises(ff.FuseFlowError):
+            ctx.fuse([bad] + dev["cams"][1:], dev["depth"], dev["conf"])

@@ -474,6 +474,31 @@ def test_empty_and_degenerate_frames():
     assert r["debug"]["e"] == O.E_MIN and r["reps"][0].tolist() == [3 * 16 + 5, O.PAD, O.PAD]
 
 
+def _bad_cameras(cam):
+    import dataclasses
+    T = cam.world_to_cam.copy()
+    T[1, 3] = np.inf
+    return [dataclasses.replace(cam, fx=0.0), dataclasses.replace(cam, fy=2.0 ** -21),
+            dataclasses.replace(cam, fx=2.0 ** 21), dataclasses.replace(cam, fx=np.nan),
+            dataclasses.replace(cam, cx=16385.0), dataclasses.replace(cam, cy=-np.inf),
+            dataclasses.replace(cam, world_to_cam=T)]
+
+
+def test_camera_validation():
+    import dataclasses
+    cam = make_camera(4, 4, np.array([0.0, -3, 0]), np.zeros(3))
+    D = [np.ones((4, 4), F32)]
+    C = [np.ones((4, 4), F32)]
+    for bad in _bad_cameras(cam):
+        with pytest.raises(ValueError):
+            O.fuse([bad], D, C)
+    with pytest.raises(ValueError):
+        O.validate_camera(dataclasses.replace(cam, width=16385))
+    # the edges of the admitted range are accepted
+    O.fuse([dataclasses.replace(cam, fx=2.0 ** 20, fy=-(2.0 ** -20), cx=16384.0, cy=-16384.0)],
+           D, C)
+
+
 def test_parameter_validation():
     cam = make_camera(4, 4, np.array([0.0, -3, 0]), np.zeros(3))
     D = [np.ones((4, 4), F32)]
