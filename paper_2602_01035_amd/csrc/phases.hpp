@@ -1498,39 +1498,49 @@ __device__ __forceinline__ void top3_insert(const CellCtx& X, Cand* rep, int& n,
     if (n < 3) ++n;
 }
 
-// The best three members by confidence alone (sorted positions k).  `tie` is set whenever
-// a confidence equal to a kept one is met: only then can the position/pixel tie-break of
-// the full order change the result, and the caller ranks that cell again in full.
+// The best three members by confidence alone, as 64-bit keys: the complemented
+// order-preserving bits of C (-0 taken as +0), so that a larger confidence is a smaller
+// key, then the sorted position k.  A branch-free insertion keeps the three smallest keys
+// in order (an empty slot holds the largest key, which no confidence produces).  `tie` is
+// set whenever a confidence equal to a kept one is met: only then can the position/pixel
+// tie-break of the full order change the result, and the caller ranks that cell again in
+// full.
+constexpr uint64_t kNoKey = ~0ull;
 struct Top3 {
-    float C0, C1, C2;
-    uint32_t k0, k1, k2;
-    int n;
+    uint64_t key[3];
     bool tie;
 };
 
-__device__ __forceinline__ void top3c_insert(Top3& t, float c, uint32_t k) {
-    if ((t.n > 0 && c == t.C0) || (t.n > 1 && c == t.C1) || (t.n > 2 && c == t.C2)) t.tie = true;
-    if (t.n == 3 && !(c > t.C2)) return;
-    if (t.n < 1 || c > t.C0) {
-        t.C2 = t.C1; t.k2 = t.k1; t.C1 = t.C0; t.k1 = t.k0; t.C0 = c; t.k0 = k;
-    } else if (t.n < 2 || c > t.C1) {
-        t.C2 = t.C1; t.k2 = t.k1; t.C1 = c; t.k1 = k;
-    } else {
-        t.C2 = c; t.k2 = k;
+__device__ __forceinline__ uint64_t conf_key(float c, uint32_t k) {
+    return (uint64_t)(~f2o(c + 0.0f)) << 32 | k;
+}
+__device__ __forceinline__ float key_conf(uint64_t key) { return o2f(~(uint32_t)(key >> 32)); }
+
+__device__ __forceinline__ void top3c_insert(Top3& t, uint64_t c) {
+    const uint32_t h = (uint32_t)(c >> 32);
+    const bool eq = (h == (uint32_t)(t.key[0] >> 32)) | (h == (uint32_t)(t.key[1] >> 32)) |
+                    (h == (uint32_t)(t.key[2] >> 32));
+    t.tie |= eq & (c != kNoKey);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const bool lt = c < t.key[q];
+        const uint64_t lo = lt ? c : t.key[q];
+        c = lt ? t.key[q] : c;
+        t.key[q] = lo;
     }
-    if (t.n < 3) ++t.n;
 }
 
 // merge the partner lane's list (disjoint members) into this lane's
 template <int CTRL>
 __device__ __forceinline__ void top3c_merge(Top3& t) {
-    const int pn = (int)qmov<CTRL>((uint32_t)t.n | (t.tie ? 4u : 0u));
-    const float c0 = qmovf<CTRL>(t.C0), c1 = qmovf<CTRL>(t.C1), c2 = qmovf<CTRL>(t.C2);
-    const uint32_t k0 = qmov<CTRL>(t.k0), k1 = qmov<CTRL>(t.k1), k2 = qmov<CTRL>(t.k2);
-    if (pn & 4) t.tie = true;
-    if ((pn & 3) > 0) top3c_insert(t, c0, k0);
-    if ((pn & 3) > 1) top3c_insert(t, c1, k1);
-    if ((pn & 3) > 2) top3c_insert(t, c2, k2);
+    uint64_t pk[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        pk[q] = (uint64_t)qmov<CTRL>((uint32_t)(t.key[q] >> 32)) << 32 |
+                qmov<CTRL>((uint32_t)t.key[q]);
+    t.tie |= qmov<CTRL>(t.tie ? 1u : 0u) != 0u;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) top3c_insert(t, pk[q]);
 }
 
 // Output of one cell from its representatives' values (lane 0 of the quad): joint weights
@@ -1695,9 +1705,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                 // them are loaded together (most cells give a lane one or two members),
                 // then ranked by confidence
                 Top3 t;
-                t.C0 = t.C1 = t.C2 = 0.0f;
-                t.k0 = t.k1 = t.k2 = 0;
-                t.n = 0;
+                t.key[0] = t.key[1] = t.key[2] = kNoKey;
                 t.tie = no_mf;                        // all confidences 1: full order
                 if (!no_mf) {
                     for (uint32_t k0 = start + q; k0 < end; k0 += 16u) {
@@ -1719,15 +1727,17 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj) {
                             const uint32_t k = k0 + 4u * jj;
-                            if (k < end) top3c_insert(t, cv[jj], k);
+                            top3c_insert(t, k < end ? conf_key(cv[jj], k) : kNoKey);
                         }
                     }
                 }
                 top3c_merge<kQuadXor1>(t);
                 top3c_merge<kQuadXor2>(t);
                 const int nrep = (int)min(3u, end - start);
-                uint32_t kr0 = t.k0, kr1 = t.k1, kr2 = t.k2;
-                float cr0 = t.C0, cr1 = t.C1, cr2 = t.C2;
+                uint32_t kr0 = (uint32_t)t.key[0], kr1 = (uint32_t)t.key[1],
+                         kr2 = (uint32_t)t.key[2];
+                float cr0 = key_conf(t.key[0]), cr1 = key_conf(t.key[1]),
+                      cr2 = key_conf(t.key[2]);
                 if (t.tie) {
                     // equal confidences among the best: lane 0 ranks the whole cell in the
                     // full order (confidence, then position, then pixel id)
