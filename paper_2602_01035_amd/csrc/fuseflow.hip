@@ -501,10 +501,27 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     // at once (4 per CU at its register use), so no partial second round trails the launch
     H->n_cell_items = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096));
     H->max_radix_bits = (uint32_t)c->tune.radix_bits;
-    // widest possible dense key: frames x coarse cells x 8^Lmax
-    const uint32_t bits_max = (uint32_t)(ilog2((uint32_t)n_frames) + 3 * H->prm.log2G +
-                                         3 * prm->max_level);
-    H->npass_max = (bits_max + H->max_radix_bits - 1) / H->max_radix_bits;
+    // Widest possible dense key.  The key range T is the sum over occupied coarse cells of
+    // 8^L.  A cell refined to level L >= 1 holds more than target 4^(L-1) points (level L-1
+    // did not suffice), so it spends fewer than 2^(L+2) / target key values per point; a
+    // level-0 cell spends at most one.  Hence T <= M max(1, 2^(Lmax+2) / target) with M <= P
+    // points; a forced level L gives T <= min(M, cells) 8^L; and always T <= cells 8^Lmax.
+    {
+        const uint64_t cells = (uint64_t)n_frames * G3;
+        const int lo = prm->level_override;
+        const uint64_t cap = cells << (3 * prm->max_level);
+        uint64_t bound;
+        if (lo >= 0) {
+            bound = std::min<uint64_t>(P, cells) << (3 * lo);
+        } else {
+            const uint64_t per = std::max<uint64_t>(
+                1, ((1ull << (prm->max_level + 2)) + (uint64_t)prm->target_per_cell - 1) /
+                       (uint64_t)prm->target_per_cell);
+            bound = (P > cap / per) ? cap : std::min<uint64_t>(cap, P * per);
+        }
+        const uint32_t bits_max = bound > 1 ? (uint32_t)(64 - __builtin_clzll(bound - 1)) : 0u;
+        H->npass_max = std::max<uint32_t>(1, (bits_max + H->max_radix_bits - 1) / H->max_radix_bits);
+    }
     if (H->npass_max > (uint32_t)kMaxPass) return FF_ERR_INVALID_ARG;
     plan.launches.clear();
     auto add = [&](uint32_t kind, uint32_t n, uint32_t pass) { plan.launches.push_back({kind, n, pass}); };

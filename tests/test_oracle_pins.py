@@ -507,3 +507,23 @@ def test_parameter_validation():
                 O.Params(sigma=0.0), O.Params(k_views=0)):
         with pytest.raises(ValueError):
             O.fuse([cam], D, C, params=bad)
+
+
+@pytest.mark.parametrize("target,max_level", [(16, 6), (1, 6), (4, 3), (64, 6), (16, 0), (3, 5)])
+def test_dense_key_range_bound(target, max_level):
+    """The sort is planned for at most ceil(log2 T) key bits with T, the dense key range
+    (sum over occupied coarse cells of 8^L), bounded by M max(1, ceil(2^(Lmax+2) / target)):
+    a cell refined to L >= 1 holds more than target 4^(L-1) points.  Checked on random and
+    on worst-case count vectors through the oracle's level rule."""
+    p = O.Params(target_per_cell=target, max_level=max_level)
+    per = max(1, -(-(2 ** (max_level + 2)) // target))
+    rng = np.random.default_rng(target * 7 + max_level)
+    worst = [target * 4 ** (L - 1) + 1 for L in range(1, max_level + 1)]
+    cases = [rng.integers(0, 5000, 4096), rng.integers(0, 50, 4096),
+             np.array(worst + [1, 1, 0], np.int64), np.array([worst[-1]] * 5 if worst else [1])]
+    for counts in cases:
+        counts = np.asarray(counts, np.int64)
+        L = O.levels(counts, p)
+        T = int(np.sum(np.where(counts > 0, 8 ** L, 0)))
+        M = int(counts.sum())
+        assert T <= M * per, (counts[:8], T, M * per)
