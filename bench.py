@@ -176,7 +176,6 @@ def run_regimes(ff, torch, params, stream, args):
         dt = run(srv, steps)
         st = srv.stats()
         row[name] = {"px_s": steps * sum(Pr) / dt, "steps": steps,
-                     "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                      "mean_batch_frames": st["mean_batch_frames"]}
         srv.close()
     row["speedup_serving_vs_plain"] = row["serving"]["px_s"] / row["plain"]["px_s"]
@@ -471,11 +470,13 @@ def main():
                    "frames_per_step": N_RIGS, "pixels_per_frame": P, "lanes": args.lanes,
                    "max_batch_frames": args.batch, "params": "tau 0.6, K 4, sigma 0.02, "
                    "coarse 64, max level 6, target 16"},
+        # saturation: every frame is submitted at once, so completion times measure the queue;
+        # frame latency under arrivals is in "latency"
         "serving": {"px_s": px_srv, "ms_per_frame": dt_srv / n_srv * 1e3,
                     "mean_batch_frames": st_srv["mean_batch_frames"],
-                    "p50_ms": st_srv["p50_ms"], "p99_ms": st_srv["p99_ms"]},
+                    "saturation_p50_ms": st_srv["p50_ms"], "saturation_p99_ms": st_srv["p99_ms"]},
         "plain": {"px_s": px_pl, "ms_per_frame": dt_pl / n_pl * 1e3,
-                  "p50_ms": st_pl["p50_ms"], "p99_ms": st_pl["p99_ms"]},
+                  "saturation_p50_ms": st_pl["p50_ms"], "saturation_p99_ms": st_pl["p99_ms"]},
         "speedup_serving_vs_plain": px_srv / px_pl,
         "fused_points_per_s": fused_per_s,
         "frame_sizes": {"P": P, "M": M_mean, "S": S_mean, "R": R_mean},
