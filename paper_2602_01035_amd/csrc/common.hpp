@@ -137,8 +137,8 @@ enum PhaseKind : uint32_t {
     PH_CAM_PREP = 15, PH_CONF = 16, PH_COUNT = 17
 };
 
-constexpr int kEmcBlocks = 2048;
-constexpr int kHistTiles = 4;            // pixel tiles per coarse-histogram workgroup          // workgroups of the E_MC evaluator
+constexpr int kEmcBlocks = 2048;         // workgroups of the E_MC evaluator
+constexpr int kHistTiles = 4;            // pixel tiles per coarse-histogram workgroup
 
 // trace slot of the Eq. 3 confidence phase (the radix passes use 16 .. 30)
 constexpr int kTraceSlotConf = 31;
