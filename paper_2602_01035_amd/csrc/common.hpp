@@ -127,7 +127,6 @@ struct BatchState {
     uint64_t T_tot;
     uint32_t pass_shift[kMaxPass];
     uint32_t pass_bits[kMaxPass];
-    uint32_t scan_done[kMaxPass];    // digit workgroups of a pass whose column scan finished
 };
 
 enum PhaseKind : uint32_t {

@@ -153,7 +153,7 @@ size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits) {
         case PH_TILE_REDUCE: return (8 + 32) * 4;
         case PH_HIST: return kHashSlots * 8;
         case PH_RADIX_UP: return ((size_t)1 << bits) * 4;
-        case PH_RADIX_SCAN: return (16 + ((size_t)1 << bits)) * 4;    // + the digit bases
+        case PH_RADIX_SCAN: return 16 * 4;
         case PH_RADIX_DOWN: return down_smem(items, bits, ncams);
         case PH_HEAD_WRITE: return kMaxFrames * 8 + 16;
         case PH_CELLS: return cells_smem(ncams);

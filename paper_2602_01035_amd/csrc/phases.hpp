@@ -594,7 +594,6 @@ __device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* sme
     if (tid == 0) {
         bs.M_tot = 0; bs.S_tot = 0; bs.error = 0; bs.key64 = 0;
         bs.key_bits = 0; bs.npass = 0; bs.T_tot = 0;
-        for (int k = 0; k < kMaxPass; ++k) bs.scan_done[k] = 0;
     }
     uint32_t carry = 0;
     for (uint32_t f = 0; f < H.n_frames; ++f) {
@@ -1039,26 +1038,7 @@ __device__ __forceinline__ void ph_radix_scan(const Ctx& C, uint32_t pass, uint3
         }
         carry += tot;
     }
-    // the digit workgroup that finishes last turns the digit totals into the digits' first
-    // output positions (exclusive scan over digits, in place) for every scatter tile: a
-    // release fence before counting itself done, an acquire fence before reading the others
-    uint32_t* s_last = s_w + 8;
-    if (threadIdx.x == 0) {
-        C.digit_total[d] = carry;
-        __threadfence();
-        *s_last = atomicAdd(&bs->scan_done[pass], 1u) == D - 1 ? 1u : 0u;
-    }
-    __syncthreads();
-    if (*s_last) {
-        __threadfence();
-        uint32_t* s_tot = s_w + 16;                                     // [D]
-        for (uint32_t i = threadIdx.x; i < D; i += kBlock)
-            s_tot[i] = __hip_atomic_load(&C.digit_total[i], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        (void)lds_excl_scan(s_tot, D, s_w);
-        for (uint32_t i = threadIdx.x; i < D; i += kBlock) C.digit_total[i] = s_tot[i];
-    }
+    if (threadIdx.x == 0) C.digit_total[d] = carry;
 }
 
 template <typename K, int ITEMS>
@@ -1097,10 +1077,13 @@ __device__ void radix_down(const Ctx& C, uint32_t pass, uint32_t tile, char* sme
     if (last)
         for (uint32_t i = tid; i < nc; i += kBlock) s_cam[i] = C.camlite[i].pix_off;
     for (uint32_t i = tid; i < 4 * D; i += kBlock) s_wc[i] = 0;
-    // digit starts (scanned once per pass by the column-scan kernel) plus this tile's
-    // offset within each digit (its row was scanned over the tiles)
-    for (uint32_t d = tid; d < D; d += kBlock)
-        s_gb[d] = C.digit_total[d] + C.digit_hist[(uint64_t)d * nt + tile];
+    // digit starts (an exclusive scan of the digit totals, done in every workgroup: D values
+    // from L2, cheaper than ordering a separate scan after all column scans) plus this
+    // tile's offset within each digit (its row was scanned over the tiles)
+    for (uint32_t d = tid; d < D; d += kBlock) s_gb[d] = C.digit_total[d];
+    __syncthreads();
+    (void)lds_excl_scan(s_gb, D, s_w);
+    for (uint32_t d = tid; d < D; d += kBlock) s_gb[d] += C.digit_hist[(uint64_t)d * nt + tile];
 
     const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
     uint32_t* wc = s_wc + w * D;
