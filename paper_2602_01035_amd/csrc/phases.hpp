@@ -328,18 +328,19 @@ __device__ __forceinline__ void camera_centre(DevCam& cm) {
 
 // ---------------------------------------------------------------- per-pixel tile walk
 
-// Visit the 16 pixels of this thread in tile `tile` (4 groups of 4 consecutive pixels, the
-// groups 1024 pixels apart, so that a wave reads 1 KiB contiguous per load).  f(g, j, x, y,
-// d, c, in_range, index) is called in pixel order for each thread.
-template <typename F>
-__device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile, F&& f) {
+// A pixel tile is 4096 pixels of one camera, 16 per thread: 4 groups of 4 consecutive
+// pixels, the groups 1024 pixels apart, so that a wave reads 1 KiB contiguous per load.
+// Thread t holds pixels base + g * 1024 + 4 t + j (g < 4, j < 4), loaded as float4 where
+// aligned.
+struct TileData {
+    float d[kPxPerThread / 4][4], c[kPxPerThread / 4][4];
+};
+
+// every load of the thread (16 depths and 16 confidences in flight)
+__device__ __forceinline__ void load_tile(const DevCam& cm, uint32_t tile, TileData& t) {
     const uint32_t npx = (uint32_t)cm.W * (uint32_t)cm.H;
     const uint32_t base = (tile - cm.tile_off) * (uint32_t)kPxTile;
-    const uint32_t W = (uint32_t)cm.W;
     constexpr int NG = kPxPerThread / 4;
-    // every load of the thread first (16 depths and 16 confidences in flight), then the
-    // pixels in order: the work on one group does not wait for the next group's loads
-    float d[NG][4], c[NG][4];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const uint32_t idx = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
@@ -347,17 +348,27 @@ __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile,
             typedef float f4 __attribute__((ext_vector_type(4)));
             const f4 dv = *glob(reinterpret_cast<const f4*>(cm.depth + idx));
             const f4 cv = *glob(reinterpret_cast<const f4*>(cm.conf + idx));
-            d[g][0] = dv.x; d[g][1] = dv.y; d[g][2] = dv.z; d[g][3] = dv.w;
-            c[g][0] = cv.x; c[g][1] = cv.y; c[g][2] = cv.z; c[g][3] = cv.w;
+            t.d[g][0] = dv.x; t.d[g][1] = dv.y; t.d[g][2] = dv.z; t.d[g][3] = dv.w;
+            t.c[g][0] = cv.x; t.c[g][1] = cv.y; t.c[g][2] = cv.z; t.c[g][3] = cv.w;
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bool in = idx + j < npx;
-                d[g][j] = in ? glob(cm.depth)[idx + j] : 0.0f;
-                c[g][j] = in ? glob(cm.conf)[idx + j] : 0.0f;
+                t.d[g][j] = in ? glob(cm.depth)[idx + j] : 0.0f;
+                t.c[g][j] = in ? glob(cm.conf)[idx + j] : 0.0f;
             }
         }
     }
+}
+
+// the pixels of a loaded tile in order: f(g, j, x, y, depth, confidence, in image, index)
+template <typename F>
+__device__ __forceinline__ void visit_tile(const DevCam& cm, uint32_t tile, const TileData& t,
+                                           F&& f) {
+    const uint32_t npx = (uint32_t)cm.W * (uint32_t)cm.H;
+    const uint32_t base = (tile - cm.tile_off) * (uint32_t)kPxTile;
+    const uint32_t W = (uint32_t)cm.W;
+    constexpr int NG = kPxPerThread / 4;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const uint32_t idx = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
@@ -365,10 +376,19 @@ __device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile,
         uint32_t x = idx - y * W;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            f(g, j, x, y, d[g][j], c[g][j], idx + j < npx, idx + j);
+            f(g, j, x, y, t.d[g][j], t.c[g][j], idx + j < npx, idx + j);
             if (++x == W) { x = 0; ++y; }
         }
     }
+}
+
+// every load of the thread first, then the pixels in order: the work on one group does
+// not wait for the next group's loads
+template <typename F>
+__device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile, F&& f) {
+    TileData t;
+    load_tile(cm, tile, t);
+    visit_tile(cm, tile, t, f);
 }
 
 // ---------------------------------------------------------------- Eq. 3 confidence
@@ -671,8 +691,8 @@ __device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* sme
 
 // one pixel tile into the LDS hash (counts: the frame's, for the rare full-hash case)
 __device__ __forceinline__ void hist_tile(const Ctx& C, const DevCam& cm, uint32_t tile,
-                                          uint32_t* s_key, uint32_t* s_cnt, uint32_t* counts,
-                                          bool no_mf) {
+                                          const TileData& td, uint32_t* s_key, uint32_t* s_cnt,
+                                          uint32_t* counts, bool no_mf) {
     const DevParams& P = C.hdr->prm;
     const float* rx = C.raytab + cm.tab_off;
     const float* ry = rx + cm.W;
@@ -700,20 +720,18 @@ __device__ __forceinline__ void hist_tile(const Ctx& C, const DevCam& cm, uint32
         const bool head = l == 0 || prev != kk;
         const bool tail = l == 63 || next != kk;
         const uint32_t incl = wave_incl(n);
-        uint32_t hs = head ? l : 0u;                   // first lane of this lane's run
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(hs, o);
-            if (l >= (uint32_t)o) hs = max(hs, t);
-        }
+        // first lane of this lane's run: the highest run head at or below it (lane 0 is one)
+        const uint64_t heads = __ballot(head);
+        const uint64_t le = l == 63u ? ~0ull : ((2ull << l) - 1ull);
+        const uint32_t hs = 63u - (uint32_t)__clzll((long long)(heads & le));
         const uint32_t before = __shfl(incl, hs == 0 ? 0 : (int)hs - 1);
         const uint32_t tot = incl - (hs == 0 ? 0u : before);
         if (tail && kk != kPad && tot) hash_add(key, tot);
     };
     uint32_t kk[4];
     bool hv[4];
-    for_tile_pixels(cm, tile, [&](int, int j, uint32_t x, uint32_t y, float d, float c, bool in,
-                                  uint32_t) {
+    visit_tile(cm, tile, td, [&](int, int j, uint32_t x, uint32_t y, float d, float c, bool in,
+                                 uint32_t) {
         bool has = in && gate_px(d, c, P.tau, no_mf);
         uint32_t key = 0;
         if (has) {
@@ -773,13 +791,25 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem)
         }
         __syncthreads();
     };
-    for (uint32_t tile = t0; tile < t1; ++tile) {
-        const DevCam& cm = C.cams[cam_of_tile(C, tile)];
+    // the next tile's loads are issued before this tile's work (two buffers in registers)
+    TileData buf[2];
+    const DevCam* cur = &C.cams[cam_of_tile(C, t0)];
+    load_tile(*cur, t0, buf[0]);
+#pragma unroll
+    for (int i = 0; i < kHistTiles; ++i) {
+        const uint32_t tile = t0 + (uint32_t)i;
+        if (tile >= t1) break;
+        const DevCam& cm = *cur;
+        if (tile + 1 < t1) {
+            cur = &C.cams[cam_of_tile(C, tile + 1)];
+            load_tile(*cur, tile + 1, buf[(i + 1) & 1]);
+        }
         if (cm.frame != frame) {
             flush(frame);
             frame = cm.frame;
         }
-        hist_tile(C, cm, tile, s_key, s_cnt, C.counts + (uint64_t)cm.frame * G3, no_mf);
+        hist_tile(C, cm, tile, buf[i & 1], s_key, s_cnt, C.counts + (uint64_t)cm.frame * G3,
+                  no_mf);
     }
     flush(frame);
 }
