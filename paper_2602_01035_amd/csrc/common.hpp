@@ -8,7 +8,7 @@ constexpr int kBlock = 256;              // threads per workgroup in every phase
 constexpr int kWave = 64;                // CDNA wavefront
 constexpr int kPxPerThread = 16;         // pixels per thread in the per-pixel phases
 constexpr int kPxTile = kBlock * kPxPerThread;   // 4096 pixels per tile (never spans cameras)
-constexpr int kScanTile = kBlock * 16;   // coarse cells per scan tile
+constexpr int kScanTile = kBlock * 4;    // coarse cells per scan tile (256 workgroups for a 64^3 grid)
 constexpr int kMaxPass = 16;             // radix passes
 constexpr int kMaxRadixBits = 10;        // widest radix digit
 constexpr int kMaxDigits = 1 << kMaxRadixBits;

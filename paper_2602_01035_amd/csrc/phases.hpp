@@ -885,7 +885,7 @@ __device__ __forceinline__ void ph_scan_b(const Ctx& C, uint32_t tile, char* sme
     const uint64_t per_frame = (uint64_t)(P.G * P.G * P.G);
     const uint64_t total = H.n_counts;
     uint64_t* s_w = reinterpret_cast<uint64_t*>(smem);
-    constexpr int kPer = kScanTile / kBlock;       // 16 consecutive cells per thread
+    constexpr int kPer = kScanTile / kBlock;       // consecutive cells per thread
     const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)threadIdx.x * kPer;
     uint64_t sp[kPer];
     uint64_t s = 0;
