@@ -528,7 +528,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     if (conf_eq3) add(PH_CONF, ntile, 0);
     add(PH_CAM_PREP, ncam, 0);
     add(PH_BACKPROJECT, ntile, 0);
-    add(PH_TILE_REDUCE, 1, 0);
+    add(PH_TILE_REDUCE, (uint32_t)n_frames, 0);
     if (!no_sa) {
         add(PH_HIST, (ntile + kHistTiles - 1) / kHistTiles, 0);
         add(PH_SCAN_A, H->n_scan_tiles, 0);

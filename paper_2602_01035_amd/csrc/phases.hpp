@@ -501,6 +501,12 @@ __device__ __forceinline__ void emc_point(const DevCam* cams, int ncams, const P
 // and (y - cy)/fy per row, so that no per-pixel step divides.
 
 __device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem) {
+    if (i == 0 && threadIdx.x == 0) {
+        // the call's batch-wide state, read or counted by every later launch of the call
+        BatchState& bs = *C.bs;
+        bs.M_tot = 0; bs.S_tot = 0; bs.error = 0; bs.key64 = 0;
+        bs.key_bits = 0; bs.npass = 0; bs.T_tot = 0;
+    }
     DevCam& cm = C.cams[i];
     const DevFrame& fr = C.frames[cm.frame];
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
@@ -601,87 +607,78 @@ __device__ __forceinline__ void ph_backproject(const Ctx& C, uint32_t tile, char
 }
 
 // ---------------------------------------------------------------- phase: per-frame reduce
-// One workgroup: per-frame AABB, point count and coarse grid (Sec. II.5(1)b-c), the
-// compaction offset of every pixel tile, camera centres and their tie-break ranks.
+// One workgroup per frame: the frame's AABB, point count and coarse grid (Sec. II.5(1)b-c)
+// and the frame-local compaction offset of every pixel tile.  The frames' first compacted
+// positions (prefix of the counts over frames) are added by the keys phase.
 
-__device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t, char* smem) {
+__device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t f, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
+    if (f >= H.n_frames) return;
     const uint32_t tid = threadIdx.x, w = tid / kWave;
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);          // [8]
     uint32_t* s_r = s_w + 8;                                    // [4][8]
-    BatchState& bs = *C.bs;
-    if (tid == 0) {
-        bs.M_tot = 0; bs.S_tot = 0; bs.error = 0; bs.key64 = 0;
-        bs.key_bits = 0; bs.npass = 0; bs.T_tot = 0;
-    }
+    const DevFrame& fr = C.frames[f];
+    uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
     uint32_t carry = 0;
-    for (uint32_t f = 0; f < H.n_frames; ++f) {
-        const DevFrame& fr = C.frames[f];
-        uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
-        const uint32_t key_begin = carry;
-        // 8 consecutive tiles per thread per step: their loads are in flight together
-        constexpr int kPer = 8;
-        for (uint32_t b = 0; b < fr.n_tiles; b += kBlock * kPer) {
-            uint32_t c[kPer], sum = 0;
+    // 8 consecutive tiles per thread per step: their loads are in flight together
+    constexpr int kPer = 8;
+    for (uint32_t b = 0; b < fr.n_tiles; b += kBlock * kPer) {
+        uint32_t c[kPer], sum = 0;
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-                const uint32_t i = b + tid * kPer + j;
-                const bool in = i < fr.n_tiles;
-                TilePart tp;
-                if (in) tp = C.tiles[fr.tile_begin + i];
-                c[j] = in ? tp.cnt : 0u;
-                if (in && c[j]) {
-                    for (int a = 0; a < 3; ++a) {
-                        mn[a] = min(mn[a], tp.mn[a]);
-                        mx[a] = max(mx[a], tp.mx[a]);
-                    }
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = b + tid * kPer + j;
+            const bool in = i < fr.n_tiles;
+            TilePart tp;
+            if (in) tp = C.tiles[fr.tile_begin + i];
+            c[j] = in ? tp.cnt : 0u;
+            if (in && c[j]) {
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = min(mn[a], tp.mn[a]);
+                    mx[a] = max(mx[a], tp.mx[a]);
                 }
-                sum += c[j];
             }
-            uint32_t tot;
-            uint32_t run = carry + block_excl(sum, s_w, tot);
-#pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-                const uint32_t i = b + tid * kPer + j;
-                if (i < fr.n_tiles) C.tile_off[fr.tile_begin + i] = run;
-                run += c[j];
-            }
-            carry += tot;
+            sum += c[j];
         }
+        uint32_t tot;
+        uint32_t run = carry + block_excl(sum, s_w, tot);
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                mn[a] = min(mn[a], (uint32_t)__shfl_xor(mn[a], o));
-                mx[a] = max(mx[a], (uint32_t)__shfl_xor(mx[a], o));
-            }
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = b + tid * kPer + j;
+            if (i < fr.n_tiles) C.tile_off[fr.tile_begin + i] = run;
+            run += c[j];
         }
-        if (lane_id() == 0)
-            for (int a = 0; a < 3; ++a) { s_r[w * 8 + a] = mn[a]; s_r[w * 8 + 3 + a] = mx[a]; }
-        __syncthreads();
-        if (tid == 0) {
-            FrameState& st = C.fs[f];
-            float lo[3], hi[3];
-            for (int a = 0; a < 3; ++a) {
-                st.bmin_o[a] = min(min(s_r[a], s_r[8 + a]), min(s_r[16 + a], s_r[24 + a]));
-                st.bmax_o[a] = max(max(s_r[3 + a], s_r[11 + a]), max(s_r[19 + a], s_r[27 + a]));
-                lo[a] = o2f(st.bmin_o[a]);
-                hi[a] = o2f(st.bmax_o[a]);
-                st.bmin[a] = lo[a];
-            }
-            st.e = coarse_exponent(lo, hi, P.log2G);
-            st.scale = __uint_as_float((uint32_t)(127 - st.e) << 23);
-            st.M = carry - key_begin;
-            st.key_begin = key_begin;
-            st.cell_begin = 0;
-            st.has_cells = 0;
-            st.fine_begin = 0;
-            for (int k = 0; k < kRSlots; ++k) st.R[k] = 0;
-        }
-        __syncthreads();
+        carry += tot;
     }
-    if (tid == 0) bs.M_tot = carry;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = min(mn[a], (uint32_t)__shfl_xor(mn[a], o));
+            mx[a] = max(mx[a], (uint32_t)__shfl_xor(mx[a], o));
+        }
+    }
+    if (lane_id() == 0)
+        for (int a = 0; a < 3; ++a) { s_r[w * 8 + a] = mn[a]; s_r[w * 8 + 3 + a] = mx[a]; }
+    __syncthreads();
+    if (tid == 0) {
+        FrameState& st = C.fs[f];
+        float lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            st.bmin_o[a] = min(min(s_r[a], s_r[8 + a]), min(s_r[16 + a], s_r[24 + a]));
+            st.bmax_o[a] = max(max(s_r[3 + a], s_r[11 + a]), max(s_r[19 + a], s_r[27 + a]));
+            lo[a] = o2f(st.bmin_o[a]);
+            hi[a] = o2f(st.bmax_o[a]);
+            st.bmin[a] = lo[a];
+        }
+        st.e = coarse_exponent(lo, hi, P.log2G);
+        st.scale = __uint_as_float((uint32_t)(127 - st.e) << 23);
+        st.M = carry;
+        st.cell_begin = 0;
+        st.has_cells = 0;
+        st.fine_begin = 0;
+        for (int k = 0; k < kRSlots; ++k) st.R[k] = 0;
+    }
 }
 
 // ---------------------------------------------------------------- phase: coarse histogram
@@ -932,6 +929,21 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
     FrameGrid g;
     if (!no_sa) frame_grid(C.fs[cm.frame], P, g);
 
+    if (tile == 0) {
+        // every frame's first compacted position and the batch's point count, for the phases
+        // after this one
+        for (uint32_t f = threadIdx.x; f < H.n_frames; f += kBlock) {
+            uint32_t k = 0;
+            for (uint32_t h = 0; h < f; ++h) k += C.fs[h].M;
+            C.fs[f].key_begin = k;
+        }
+        if (threadIdx.x == 0) {
+            uint32_t m = 0;
+            for (uint32_t h = 0; h < H.n_frames; ++h) m += C.fs[h].M;
+            bs->M_tot = m;
+        }
+    }
+
     uint64_t kv[kPxPerThread];
     uint32_t mask = 0;
     for_tile_pixels(cm, tile, [&](int gi, int j, uint32_t x, uint32_t y, float d, float c,
@@ -959,7 +971,12 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
         off[gi] = tile_total + block_excl(c, s_w, tot);
         tile_total += tot;
     }
-    const uint32_t pre = C.tile_off[tile];
+    // the frame's first compacted position: the points of the frames before it (each wave
+    // sums them itself; at most kMaxFrames counts)
+    uint32_t kb = 0;
+    for (uint32_t g = lane_id(); g < cm.frame; g += kWave) kb += C.fs[g].M;
+    kb = (uint32_t)wave_sum64(kb);
+    const uint32_t pre = kb + C.tile_off[tile];
     const uint32_t pbase = cm.pix_off + (tile - cm.tile_off) * (uint32_t)kPxTile;
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
