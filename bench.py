@@ -18,7 +18,8 @@ Before them, every input frame goes once through ff_fuse (its M, S, R give the a
 bytes) and one frame is traced kernel by kernel (HIP events) to name the dominant kernel.
 After them, a timed region of the same steps in the serving batch size, batched calls one
 after another on the caller's stream, times that kernel alone with events around it
-(roofline), and the CPU oracle runs on a bounded sample (cpu_baseline).
+(roofline), and the CPU oracle runs on a bounded sample (cpu_baseline); the same frames go
+through the server in the timed configuration and are checked against the oracle's output.
 --copy-calibration MiB first runs a plain elementwise copy (read N, write N bytes) so that
 hardware byte counters of the same profiled run can be scaled.
 Prints ONE JSON line.
@@ -99,6 +100,42 @@ def frame_alg_bytes(P, M, S, R, K):
     """Whole-frame algorithmic bytes of the method (three traversals of D and C, one key
     write, one grouping scatter, segmentation/ranking, consistency gathers, output)."""
     return 24 * P + 52 * M + (8 + 4 * (K - 1)) * R + 16 * S
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def serving_parity(ff, torch, np, O, frames, devs, oracle_out, P, params, args):
+    """The oracle's frames through the continuous-batching server in the timed configuration:
+    count, keys, member counts and representatives bit for bit, fused coordinates and
+    weights within 1e-5 (relative; floors 1 m and 1e-6), colours within 1."""
+    srv = ff.Server(hbm_budget_bytes=8 << 30, lanes=args.lanes, max_batch_frames=args.batch)
+    outs = [ff.Output(P, rgb=True) for _ in devs]
+    for i, d in enumerate(devs):
+        srv.submit(i, d, outs[i], params)
+    srv.drain()
+    srv.close()
+    ok, worst_xyz, worst_w = True, 0.0, 0.0
+    for o, g in zip(oracle_out, (x.result() for x in outs)):
+        same = (g["status"] == 0 and g["count"] == len(o["keys"]) and
+                all(np.array_equal(g[k], o[k]) for k in ("keys", "n_members", "reps")))
+        scale = np.maximum(np.abs(o["xyz"]).max(axis=1), 1.0)
+        ex = float((np.abs(g["xyz"].astype(np.float64) - o["xyz"]).max(axis=1) / scale).max())
+        ew = float((np.abs(g["weight"].astype(np.float64) - o["weight"]) /
+                    np.maximum(o["weight"], 1e-6)).max())
+        rgb_ok = int(np.abs(g["rgb"].astype(int) - o["rgb"].astype(int)).max()) <= 1
+        ok = ok and same and ex <= 1e-5 and ew <= 1e-5 and rgb_ok
+        worst_xyz, worst_w = max(worst_xyz, ex), max(worst_w, ew)
+    return {"frames": len(devs), "ok": bool(ok), "max_rel_xyz_err": worst_xyz,
+            "max_rel_weight_err": worst_w}
 
 
 MALL_BYTES = 256 << 20
@@ -459,16 +496,19 @@ def main():
         from oracle import core as O
         sample = [(0, f) for f in range(min(2, args.frames_per_rig))]
         c0, w0 = time.process_time(), time.perf_counter()
-        for key in sample:
-            O.fuse_frame(frames[key])
+        oracle_out = [O.fuse_frame(frames[key]) for key in sample]
         wall = time.perf_counter() - w0
         cpu_t = time.process_time() - c0
         cpu = {"value": len(sample) * P / wall, "unit": "px/s",
                "cores": max(1, round(cpu_t / wall)), "kind": "oracle",
                "sample": f"{len(sample)} frame(s) of rig 0 (8 x 1280x720 = {P} px each) "
                          f"through the NumPy oracle, {wall:.1f} s wall, "
-                         f"{os.cpu_count()} host CPUs visible"}
+                         f"{os.cpu_count()} host CPUs visible ({cpu_model()})"}
         log(f"oracle {wall / len(sample):.1f} s per frame")
+        # the same frames through the timed serving configuration, against the oracle
+        cpu["parity"] = serving_parity(ff, torch, np, O, [frames[k] for k in sample],
+                                       [devs[k] for k in sample], oracle_out, P, params, args)
+        log(f"parity of the served frames against the oracle: {cpu['parity']}")
 
     line = {
         "metric": METRIC, "value": px_srv, "unit": "px/s", "n_gpus": 1, "steps": args.steps,
