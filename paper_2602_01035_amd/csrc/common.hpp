@@ -66,8 +66,6 @@ struct CamLite {
     const float* depth;
     const float* conf;
     const uint8_t* rgb;
-    const float* rx;         // (x - cx) / fx for every column
-    const float* ry;         // (y - cy) / fy for every row
 };
 
 struct DevFrame {

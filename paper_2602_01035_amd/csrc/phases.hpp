@@ -539,8 +539,6 @@ __device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem
         cl.W = me.W; cl.H = me.H; cl.rank = rank; cl.pix_off = me.pix_off;
         cl.invW = 1.0f / (float)me.W;
         cl.depth = me.depth; cl.conf = me.conf; cl.rgb = me.rgb;
-        cl.rx = rx;
-        cl.ry = ry;
         C.camlite[i] = cl;
     }
 }
