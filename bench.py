@@ -74,9 +74,9 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # sources they were taken on (their digest); otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "ba0fa36cb351a0ad",
-    "fetch_kib_per_frame": 83780.9,
-    "write_kib_per_frame": 53599.1,
+    "source_digest": "5775f9b94ad7deb1",
+    "fetch_kib_per_frame": 83793.1,
+    "write_kib_per_frame": 53597.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -237,8 +237,8 @@ def run_regimes(ff, torch, params, stream, args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=25)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--frames-per-rig", type=int, default=2)
     ap.add_argument("--rates", default="1,8,12", help="Poisson rate multipliers of 30 Hz/rig")
     ap.add_argument("--trace-seconds", type=float, default=2.0)
