@@ -103,6 +103,28 @@ def test_empty_and_single_pixel(ctx, ff):
     assert g["count"] == 1 and g["weight"][0] == np.float32(0.75)
 
 
+def test_batch_with_empty_frames(ctx, ff):
+    """Frames without a single gated point between others in one batched call: every
+    frame's compacted positions start after the points of the frames before it."""
+    import synth
+    cam = make_camera(37, 5, np.array([0.0, -3, 0]), np.zeros(3))
+    empty = synth.Frame([cam], [np.zeros((5, 37), np.float32)], [np.ones((5, 37), np.float32)],
+                        None, None, None, None, [])
+    D1 = np.zeros((5, 37), np.float32)
+    C1 = np.ones((5, 37), np.float32)
+    D1[2, 11] = 2.0
+    C1[2, 11] = 0.75
+    single = synth.Frame([cam], [D1], [C1], None, None, None, None, [])
+    frames = [empty, cached_frame("c1"), empty, single, cached_frame("c1", frame=1), empty]
+    print("[case] batch of 6 with empty frames", flush=True)
+    devs = [ff.to_device(f, with_rgb=False) for f in frames]
+    outs = ctx.fuse_batch(devs, members=True)
+    for i, (f, out) in enumerate(zip(frames, outs)):
+        g = out.result()
+        compare(g, O.fuse_frame(f, with_rgb=False), label=f"frame {i}")
+    assert outs[0].result()["count"] == 0 and outs[3].result()["count"] == 1
+
+
 def test_nonfinite_inputs(ctx, ff):
     f = make_config("c1")
     D = [d.copy() for d in f.depth]
