@@ -1702,7 +1702,11 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
     const uint32_t r1 = (uint32_t)((uint64_t)S * (xcd + 1) / nx);
     for (uint32_t g0 = r0 + (li * wpb + wave) * kStageCells; g0 < r1;
          g0 += n_local * wpb * kStageCells) {
-        // member ranges of all 64 cells at once (lane = cell), handed to the quads via LDS
+        // member ranges of all 64 cells at once (lane = cell).  A cell of at most three
+        // members needs no selection: its lane loads their confidences and orders them; a
+        // tie among them goes to the quads, which settle it in the full order.  The other
+        // cells are listed for the quads.
+        bool big = false;
         {
             const uint32_t s = g0 + lane;
             uint32_t a = 0, b = 0;
@@ -1710,16 +1714,68 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                 if (no_sa) { a = s; b = s + 1; }
                 else { a = glob(C.cell_start)[s]; b = glob(C.cell_start)[s + 1]; }
             }
+            bool small = false;
+            if (s < r1 && have_cs && a < b && b <= M_tot && b - a <= 3u) {
+                const uint32_t n = b - a;
+                uint64_t kk[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    kk[r] = (uint32_t)r < n
+                                ? conf_key(__uint_as_float(glob(C.conf_sorted)[a + r]), a + r)
+                                : kNoKey;
+                // three-element sorting network, ascending key = descending confidence
+                auto cswap = [](uint64_t& x, uint64_t& y) {
+                    const uint64_t lo = x < y ? x : y, hi = x < y ? y : x;
+                    x = lo;
+                    y = hi;
+                };
+                cswap(kk[0], kk[1]);
+                cswap(kk[1], kk[2]);
+                cswap(kk[0], kk[1]);
+                const uint32_t h0 = (uint32_t)(kk[0] >> 32), h1 = (uint32_t)(kk[1] >> 32),
+                               h2 = (uint32_t)(kk[2] >> 32);
+                small = !((n > 1 && h0 == h1) || (n > 2 && h1 == h2));
+                if (small) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        if ((uint32_t)r < n) {
+                            st.sid[lane * 3 + r] = (uint32_t)kk[r];
+                            st.sC[lane * 3 + r] = key_conf(kk[r]);
+                        }
+                    }
+                    if (fr_mids_any) {
+                        const int f = last_le(sh.fpix, (int)nf, glob(vals)[a]);
+                        const DevFrame& fr = C.frames[f];
+                        if (fr.mids) {
+                            for (uint32_t k = a; k < b; ++k) {
+                                const uint32_t mo = k - sh.key_begin[f];
+                                if (mo < fr.member_capacity)
+                                    glob(fr.mids)[mo] = glob(vals)[k] - fr.pix_begin;
+                            }
+                        }
+                    }
+                }
+            }
+            big = s < r1 && !small;
             st.start[lane] = a;
             st.end[lane] = b;
+            st.bad[lane] = 0;
+        }
+        const uint64_t bigm = __ballot(big);
+        const uint32_t nbig = (uint32_t)__popcll(bigm);
+        if (big) {
+            const uint64_t below = lane == 0u ? 0ull : (~0ull >> (64u - lane));
+            st.list[__popcll(bigm & below)] = (uint8_t)lane;
         }
         wave_sync();
-        // ---- A: top-3 of 16 cells per pass, four lanes per cell
-        for (uint32_t sub = 0; sub < kStageCells / 16; ++sub) {
-            const uint32_t j = sub * 16u + (lane >> 2);
+        // ---- A: top-3 of the listed cells, 16 per pass, four lanes per cell
+        for (uint32_t sub = 0; sub < nbig; sub += 16u) {
+            const uint32_t jj = sub + (lane >> 2);
+            const bool have = jj < nbig;
+            const uint32_t j = have ? (uint32_t)st.list[jj] : 0u;
             const uint32_t s = g0 + j;
             uint32_t start = 0, end = 0;
-            bool ok = s < r1;
+            bool ok = have && s < r1;
             if (ok) {
                 start = st.start[j];
                 end = st.end[j];
@@ -1820,10 +1876,9 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             } else {
                 start = end = 0;
             }
-            if (q == 0u) {
+            if (have && q == 0u) {
                 st.start[j] = start;
                 st.end[j] = end;
-                st.bad[j] = 0;
             }
         }
         wave_sync();
