@@ -253,9 +253,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(frames would shard across GPUs with no communication; see the design notes)",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (frames "
+              "are independent and would shard across GPUs by frame or rig, with no "
+              "communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

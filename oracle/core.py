@@ -21,8 +21,8 @@ IEEE float32 with one rounding per +, -, *, / in exactly the order written here,
 fused multiply-add (NumPy float32 ufuncs applied one at a time).  Continuous quantities
 (squared distances, consistency, fusion) are computed in float64.
 
-Readings of points the paper leaves open (each is listed with its reason in the design
-notes and repeated at the function that implements it):
+Readings of points the paper leaves open (each repeated at the function that implements
+it):
   * T_i is world->camera [R | t]; Eq. 8 applies its inverse (R^T, c = -R^T t).
   * pi^-1(K, [x, y, 1], d) = d * K^-1 [x, y, 1]: depth is z-depth, pixel centres are at
     integer coordinates.

@@ -8,7 +8,7 @@ shares no code with the HIP library.
   Sec. II.2, Eq. 2-3   per-pixel measurement confidence   -> ``confidence_eq3``
   Sec. III, Eq. 12     multi-camera depth consistency     -> ``emc``
 
-Readings of what the paper leaves open (repeated in the design notes):
+Readings of what the paper leaves open:
   * Eq. 3's depth gradient G is the magnitude of the central-difference gradient in metres
     per pixel, sqrt(gx^2 + gy^2) with gx = (D(x+1) - D(x-1)) / 2; where only one horizontal
     (vertical) neighbour has a valid depth the one-sided difference with it is used, where
