@@ -144,10 +144,10 @@ size_t down_smem(int items, int bits, uint32_t ncams) {
     const size_t kt = (size_t)kBlock * items;
     return kt * 8 + kt * 4 + (4 + 2) * ((size_t)1 << bits) * 4 + 32 + (size_t)ncams * 4;
 }
-size_t cells_smem(uint32_t ncams) {
-    return cells_layout(ncams, ncams <= (uint32_t)kLdsCams).total;
+size_t cells_smem(uint32_t ncams, uint32_t nframes) {
+    return cells_layout(ncams, ncams <= (uint32_t)kLdsCams, nframes).total;
 }
-size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits) {
+size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits, uint32_t nframes) {
     switch (kind) {
         case PH_BACKPROJECT: return 4 * 8 * 4;
         case PH_TILE_REDUCE: return (8 + 32) * 4;
@@ -156,7 +156,7 @@ size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits) {
         case PH_RADIX_SCAN: return 16 * 4;
         case PH_RADIX_DOWN: return down_smem(items, bits, ncams);
         case PH_HEAD_WRITE: return kMaxFrames * 8 + 16;
-        case PH_CELLS: return cells_smem(ncams);
+        case PH_CELLS: return cells_smem(ncams, nframes);
         case PH_FINAL: return 16;
         default: return 64;
     }
@@ -381,6 +381,7 @@ struct Plan {
     bool wide_views = false;    // K - 1 > 3 kept views
     size_t desc_used = 0;       // bytes of the descriptor this call fills
     int radix_bits = 10;        // widest digit of the sort passes
+    uint32_t nframes = 0;
 };
 
 // Validate one batch and fill the host staging descriptor.  Returns the launch plan and a
@@ -485,6 +486,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     H->n_cams = ncam;
     H->lds_cams = ncam <= (uint32_t)kLdsCams ? 1u : 0u;
     plan.ncams = ncam;
+    plan.nframes = (uint32_t)n_frames;
     plan.wide_views = prm->k_views > 4;
     plan.radix_bits = c->tune.radix_bits;
     H->n_px_tiles = ntile;
@@ -658,7 +660,7 @@ void launch_cells(const Ctx& C, uint32_t ncams, const Plan& plan, hipStream_t s,
 
 template <int ITEMS>
 void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, const Plan& plan, hipStream_t s) {
-    const size_t smem = smem_for(L.kind, ITEMS, ncams, plan.radix_bits);
+    const size_t smem = smem_for(L.kind, ITEMS, ncams, plan.radix_bits, plan.nframes);
     const dim3 grid(std::max<uint32_t>(1, L.n)), block(kBlock);
 #define FF_L(K) hipLaunchKernelGGL((k_phase<K, ITEMS>), grid, block, smem, s, C, L.pass)
     switch (L.kind) {
@@ -733,10 +735,8 @@ ff_status run_graph(ff_context* c, const Ctx& C, const Plan& plan, const std::st
 // around it run as before (replayed from graphs cached per segment, or enqueued).
 ff_status run_probed(ff_context* c, const Ctx& C, const Plan& plan, const std::string& shape,
                      hipStream_t s, bool graph, uint32_t frames, uint64_t pixels) {
-    Plan seg;
-    seg.ncams = plan.ncams;
-    seg.wide_views = plan.wide_views;
-    seg.radix_bits = plan.radix_bits;
+    Plan seg = plan;            // every launch parameter of the plan, segment by segment
+    seg.launches.clear();
     int nseg = 0;
     auto flush = [&]() -> ff_status {
         if (seg.launches.empty()) return FF_OK;
@@ -776,7 +776,8 @@ ff_status set_smem_limits() {
         };
         setk((const void*)k_phase<PH_RADIX_DOWN, 8>, down_smem(8, 10, kMaxBatchCams));
         setk((const void*)k_phase<PH_RADIX_DOWN, 16>, down_smem(16, 10, kMaxBatchCams));
-        const size_t cs = std::max(cells_smem((uint32_t)kLdsCams), cells_smem((uint32_t)kMaxBatchCams));
+        const size_t cs = std::max(cells_smem((uint32_t)kLdsCams, (uint32_t)kMaxFrames),
+                                   cells_smem((uint32_t)kMaxBatchCams, (uint32_t)kMaxFrames));
         setk((const void*)k_cells<3, true>, cs);
         setk((const void*)k_cells<3, false>, cs);
         setk((const void*)k_cells<kMaxK - 1, true>, cs);

@@ -1354,13 +1354,16 @@ struct CellsShared {
 };
 
 struct CellsLayout {
-    uint32_t cam_pix, cams, stage, total;       // byte offsets, total bytes
+    uint32_t cam_pix, cams, frames, grids, stage, total;   // byte offsets, total bytes
 };
-__host__ __device__ inline CellsLayout cells_layout(uint32_t ncams, bool lds_cams) {
+__host__ __device__ inline CellsLayout cells_layout(uint32_t ncams, bool lds_cams,
+                                                    uint32_t nframes) {
     CellsLayout l;
     l.cam_pix = (uint32_t)sizeof(CellsShared);
     l.cams = (l.cam_pix + 4 * ncams + 15u) & ~15u;
-    l.stage = (l.cams + (lds_cams ? ncams * (uint32_t)sizeof(CamLite) : 0u) + 15u) & ~15u;
+    l.frames = (l.cams + (lds_cams ? ncams * (uint32_t)sizeof(CamLite) : 0u) + 15u) & ~15u;
+    l.grids = (l.frames + nframes * (uint32_t)sizeof(DevFrame) + 15u) & ~15u;
+    l.stage = (l.grids + nframes * (uint32_t)sizeof(FrameGrid) + 15u) & ~15u;
     l.total = l.stage + (uint32_t)kCellsStageBytes;
     return l;
 }
@@ -1664,7 +1667,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
     const DevParams& P = H.prm;
     BatchState* bs = C.bs;
     CellsShared& sh = *reinterpret_cast<CellsShared*>(smem);
-    const CellsLayout lay = cells_layout(H.n_cams, LDS_CAMS);
+    const CellsLayout lay = cells_layout(H.n_cams, LDS_CAMS, H.n_frames);
     uint32_t* s_cam_pix = reinterpret_cast<uint32_t*>(smem + lay.cam_pix);
     CamLite* s_cams = reinterpret_cast<CamLite*>(smem + lay.cams);
     const uint32_t nf = H.n_frames, nc = H.n_cams;
@@ -1673,11 +1676,17 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
         s_cam_pix[i] = C.camlite[i].pix_off;
         if (LDS_CAMS) s_cams[i] = C.camlite[i];
     }
+    // the frames' records and coarse grids, read by every cell: from LDS, not through
+    // dependent global loads
+    DevFrame* s_frames = reinterpret_cast<DevFrame*>(smem + lay.frames);
+    FrameGrid* s_grids = reinterpret_cast<FrameGrid*>(smem + lay.grids);
     for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
         sh.fpix[f] = C.frames[f].pix_begin;
         sh.key_begin[f] = C.fs[f].key_begin;
         sh.cell_begin[f] = no_sa ? C.fs[f].key_begin : C.fs[f].cell_begin;
         sh.rcount[f] = 0;
+        s_frames[f] = C.frames[f];
+        frame_grid(C.fs[f], P, s_grids[f]);
     }
     __syncthreads();
     const uint32_t M_tot = n_keys(C);
@@ -1745,7 +1754,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                     }
                     if (fr_mids_any) {
                         const int f = last_le(sh.fpix, (int)nf, glob(vals)[a]);
-                        const DevFrame& fr = C.frames[f];
+                        const DevFrame& fr = s_frames[f];
                         if (fr.mids) {
                             for (uint32_t k = a; k < b; ++k) {
                                 const uint32_t mo = k - sh.key_begin[f];
@@ -1864,7 +1873,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                 }
                 if (fr_mids_any) {
                     const int f = last_le(sh.fpix, (int)nf, glob(vals)[start]);
-                    const DevFrame& fr = C.frames[f];
+                    const DevFrame& fr = s_frames[f];
                     if (fr.mids) {
                         for (uint32_t k = start + q; k < end; k += 4u) {
                             const uint32_t mo = k - sh.key_begin[f];
@@ -1909,7 +1918,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             }
             ensure_p(X, mine);
             const int f = last_le(sh.fpix, (int)nf, mine.id);
-            const DevFrame& fr = C.frames[f];
+            const DevFrame& fr = s_frames[f];
             const double expo =
                 no_dc ? 0.0 : neg_log_v<KV>(cams, mine.cam, mine.p, fr.cam_begin, fr.n_cams, P);
             uint32_t rgb3 = 0;
@@ -1951,7 +1960,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                     wv[r] = h ? (double)Cr[r] * exp(-ex[r]) : 0.0;
                 }
                 const int f = last_le(sh.fpix, (int)nf, ids[0]);
-                const DevFrame& fr = C.frames[f];
+                const DevFrame& fr = s_frames[f];
                 const uint32_t o = s - sh.cell_begin[f];
                 if (o < fr.capacity) {
                     emit_cell(fr, o, nrep, Cr, pr, ex, wv, c3, ids, end - start);
@@ -1961,9 +1970,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                         if (no_sa) {
                             key = ids[0] - fr.pix_begin;
                         } else {
-                            FrameGrid g;
-                            frame_grid(C.fs[f], P, g);
-                            const CellCoord cc = coarse_cell(g, pr[0]);
+                            const CellCoord cc = coarse_cell(s_grids[f], pr[0]);
                             const int L = C.level[(uint64_t)f * G3 + cc.lin];
                             int loc[3];
                             fine_local(cc, L, loc);
