@@ -63,6 +63,9 @@ struct CamLite {
     int32_t W, H;
     uint32_t rank, pix_off;
     float invW;              // 1 / W, for a quick first guess of y = pixel / W
+    // field-of-view fast path: cx + 1/2, cy + 1/2, and the largest floats below
+    // W - m, H - m (clearly inside) and W + m, H + m (not clearly outside), m = 1/16 px
+    float cxh, cyh, in_hx, in_hy, out_hx, out_hy;
     const float* depth;
     const float* conf;
     const uint8_t* rgb;

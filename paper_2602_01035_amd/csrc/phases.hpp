@@ -180,32 +180,46 @@ __device__ __forceinline__ bool finite3(const Pt& p) {
 // nearest pixel floor(u + 1/2), floor(v + 1/2) of u = fx X/Z + cx, v = fy Y/Z + cy inside
 // the image.  The division is done only where it matters: an approximate reciprocal decides
 // points clearly inside or outside, and the exact IEEE quotients decide points near a
-// border.  The approximate u + 1/2 differs from the exact one by at most 3.6e-7 |fx X/Z|
-// plus two half-ulps of the sums; with the camera range the boundary admits (sides and
-// principal point within 2^14 px) that is < 0.04 px wherever |u| < 2^16, inside the 1/16 px
-// margin, and beyond 2^16 the point is outside by far more than the error.  "Clearly outside" is a
-// disjunction of ordered comparisons, so an approximation that is not a number (0 times
-// the infinite reciprocal of a subnormal Z) is never clearly anything and goes to the exact
-// quotients.  Written without early exits: only the rare border case branches.
+// border.  The approximate u + 1/2 (one fused multiply-add onto cx + 1/2) differs from the
+// exact one by at most 3.6e-7 |fx X/Z| plus two half-ulps of the sums; with the camera
+// range the boundary admits (sides and principal point within 2^14 px) that is < 0.04 px
+// wherever |u| < 2^16, inside the 1/16 px margin, and beyond 2^16 the point is outside by
+// far more than the error.  The ranges are tested as med3(t, lo, hi) == t, which holds
+// exactly when lo <= t <= hi and never for a NaN t; the upper ends are the largest floats
+// below W - m (clearly inside) and W + m (not clearly outside), so the tests are the
+// half-open intervals.  "Clearly outside" also needs both approximations to be numbers: an
+// approximation that is not a number (0 times the infinite reciprocal of a subnormal Z) is
+// never clearly anything and goes to the exact quotients.  Written without early exits:
+// only the rare border case branches.
+constexpr float kFovMargin = 0.0625f;
 template <typename Cam>
 __device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p) {
     const float Z = ((cm.R[6] * p.x + cm.R[7] * p.y) + cm.R[8] * p.z) + cm.t[2];
     const float X = ((cm.R[0] * p.x + cm.R[1] * p.y) + cm.R[2] * p.z) + cm.t[0];
     const float Y = ((cm.R[3] * p.x + cm.R[4] * p.y) + cm.R[5] * p.z) + cm.t[1];
     const float rz = __builtin_amdgcn_rcpf(Z);
-    const float ta = cm.fx * (X * rz) + cm.cx + 0.5f;
-    const float tb = cm.fy * (Y * rz) + cm.cy + 0.5f;
-    const float W = (float)cm.W, H = (float)cm.H, m = 0.0625f;
+    const float ta = __builtin_fmaf(cm.fx, X * rz, cm.cxh);
+    const float tb = __builtin_fmaf(cm.fy, Y * rz, cm.cyh);
+    const float m = kFovMargin;
     const bool front = Z > 0.0f;
-    const bool sure_in = (ta >= m) & (ta < W - m) & (tb >= m) & (tb < H - m);
-    const bool sure_out = (ta < -m) | (ta >= W + m) | (tb < -m) | (tb >= H + m);
+    const bool sure_in = (__builtin_amdgcn_fmed3f(ta, m, cm.in_hx) == ta) &
+                         (__builtin_amdgcn_fmed3f(tb, m, cm.in_hy) == tb);
+    const bool near = (__builtin_amdgcn_fmed3f(ta, -m, cm.out_hx) == ta) &
+                      (__builtin_amdgcn_fmed3f(tb, -m, cm.out_hy) == tb);
+    const bool sure_out = !near & !__builtin_isunordered(ta, tb);
     bool in = front & sure_in;
     if (front & !sure_in & !sure_out) {
+        const float W = (float)cm.W, H = (float)cm.H;
         const float u = cm.fx * (X / Z) + cm.cx, v = cm.fy * (Y / Z) + cm.cy;
         const float fu = floorf(u + 0.5f), fv = floorf(v + 0.5f);
         in = (fu >= 0.0f) && (fu < W) && (fv >= 0.0f) && (fv < H);
     }
     return in;
+}
+
+// the largest float below a positive finite x
+__device__ __forceinline__ float float_below(float x) {
+    return __uint_as_float(__float_as_uint(x) - 1u);
 }
 
 // exact nearest pixel of a point known to be in view (the arithmetic of the exact branch
@@ -538,6 +552,13 @@ __device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem
         cl.fx = me.fx; cl.fy = me.fy; cl.cx = me.cx; cl.cy = me.cy;
         cl.W = me.W; cl.H = me.H; cl.rank = rank; cl.pix_off = me.pix_off;
         cl.invW = 1.0f / (float)me.W;
+        cl.cxh = me.cx + 0.5f;
+        cl.cyh = me.cy + 0.5f;
+        const float Wf = (float)me.W, Hf = (float)me.H;      // exact: sides <= 2^14
+        cl.in_hx = float_below(Wf - kFovMargin);
+        cl.in_hy = float_below(Hf - kFovMargin);
+        cl.out_hx = float_below(Wf + kFovMargin);
+        cl.out_hy = float_below(Hf + kFovMargin);
         cl.depth = me.depth; cl.conf = me.conf; cl.rgb = me.rgb;
         C.camlite[i] = cl;
     }
