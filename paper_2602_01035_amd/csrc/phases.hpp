@@ -1404,12 +1404,13 @@ __device__ __forceinline__ void ensure_id(const CellCtx& X, Cand& a) {
     a.st = 1;
 }
 
-// (x, y) of pixel `loc` of a camera: a float estimate of loc / W, then exact correction
+// (x, y) of pixel `loc` of a camera: a float estimate of loc / W, then exact correction.
+// 32-bit integers suffice: loc < W H <= 2^28 and the estimate is within one row of y.
 template <typename Cam>
 __device__ __forceinline__ void pixel_xy(const Cam& cm, uint32_t loc, uint32_t& x, uint32_t& y) {
-    const int64_t W = cm.W;
-    int64_t yy = (int64_t)((float)loc * cm.invW);
-    int64_t r = (int64_t)loc - yy * W;
+    const int32_t W = cm.W;
+    int32_t yy = (int32_t)((float)loc * cm.invW);
+    int32_t r = (int32_t)loc - yy * W;
     while (r < 0) { --yy; r += W; }
     while (r >= W) { ++yy; r -= W; }
     y = (uint32_t)yy;
@@ -1569,10 +1570,10 @@ __device__ __forceinline__ uint64_t conf_key(float c, uint32_t k) {
 __device__ __forceinline__ float key_conf(uint64_t key) { return o2f(~(uint32_t)(key >> 32)); }
 
 __device__ __forceinline__ void top3c_insert(Top3& t, uint64_t c) {
-    const uint32_t h = (uint32_t)(c >> 32);
-    const bool eq = (h == (uint32_t)(t.key[0] >> 32)) | (h == (uint32_t)(t.key[1] >> 32)) |
-                    (h == (uint32_t)(t.key[2] >> 32));
-    t.tie |= eq & (c != kNoKey);
+    // equal confidence bits with a kept key: the high words differ by zero
+    const uint32_t d0 = (uint32_t)((c ^ t.key[0]) >> 32), d1 = (uint32_t)((c ^ t.key[1]) >> 32),
+                   d2 = (uint32_t)((c ^ t.key[2]) >> 32);
+    t.tie |= (min(min(d0, d1), d2) == 0u) & (c != kNoKey);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const bool lt = c < t.key[q];
