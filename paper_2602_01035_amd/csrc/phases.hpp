@@ -1440,6 +1440,20 @@ __device__ __forceinline__ bool rank_before(const CellCtx& X, Cand& a, Cand& b) 
     return a.id < b.id;
 }
 
+// Insert c into the ascending list s of the N smallest keys seen (an empty slot holds the
+// largest key).  Every comparison is against the old list, which is sorted, so slot q
+// takes s[q-1] when c goes before it, else c when c goes before s[q], else keeps s[q]:
+// N independent compares instead of a chain of minimum/maximum pairs.
+template <int N>
+__device__ __forceinline__ void insert_sorted(uint64_t (&s)[N], uint64_t c) {
+    bool b[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] = c < s[q];
+#pragma unroll
+    for (int q = N - 1; q > 0; --q) s[q] = b[q - 1] ? s[q - 1] : (b[q] ? c : s[q]);
+    s[0] = b[0] ? c : s[0];
+}
+
 // -ln V of representative (cam ri, point p): Eq. 4-7 over the first K-1 views by distance.
 // KV >= K - 1 is the compile-time size of the kept list.  Every camera of the frame is
 // tested; a visible one becomes the 64-bit key (bits of the squared distance, camera rank,
@@ -1460,15 +1474,9 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const P
         const bool vis = in_view_fast(cj, p) & ((int)j != ri);
         const float dx = p.x - cj.c[0], dy = p.y - cj.c[1], dz = p.z - cj.c[2];
         const float d2 = (dx * dx + dy * dy) + dz * dz;
-        uint64_t c = vis ? ((uint64_t)__float_as_uint(d2) << 32 | (uint64_t)cj.rank << 16 | j)
-                         : kNone;
-#pragma unroll
-        for (int q = 0; q < KV; ++q) {
-            const bool lt = c < best[q];
-            const uint64_t lo = lt ? c : best[q];
-            c = lt ? best[q] : c;
-            best[q] = lo;
-        }
+        const uint64_t c = vis ? ((uint64_t)__float_as_uint(d2) << 32 | (uint64_t)cj.rank << 16 | j)
+                               : kNone;
+        insert_sorted(best, c);
     }
     int nb = 0;
     int bj[KV];
@@ -1574,13 +1582,7 @@ __device__ __forceinline__ void top3c_insert(Top3& t, uint64_t c) {
     const uint32_t d0 = (uint32_t)((c ^ t.key[0]) >> 32), d1 = (uint32_t)((c ^ t.key[1]) >> 32),
                    d2 = (uint32_t)((c ^ t.key[2]) >> 32);
     t.tie |= (min(min(d0, d1), d2) == 0u) & (c != kNoKey);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const bool lt = c < t.key[q];
-        const uint64_t lo = lt ? c : t.key[q];
-        c = lt ? t.key[q] : c;
-        t.key[q] = lo;
-    }
+    insert_sorted(t.key, c);
 }
 
 // merge the partner lane's list (disjoint members) into this lane's
