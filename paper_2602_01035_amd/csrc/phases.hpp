@@ -142,8 +142,11 @@ __device__ __forceinline__ void raise_error(BatchState* bs, uint32_t bit) {
 __device__ __forceinline__ uint64_t match_peers(uint32_t d, bool valid, uint32_t bits) {
     uint64_t peers = __ballot(valid);
     for (uint32_t b = 0; b < bits; ++b) {
-        const uint64_t bal = __ballot((d >> b) & 1u);
-        peers &= ((d >> b) & 1u) ? bal : ~bal;
+        // m: all ones where bit b of d is set; lanes that agree on the bit are those where
+        // the ballot equals m
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, (int)b, 1);
+        const uint64_t bal = __ballot(m != 0u);
+        peers &= ~(bal ^ ((uint64_t)m << 32 | m));
     }
     return peers;
 }
