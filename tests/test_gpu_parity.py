@@ -8,7 +8,7 @@ import pytest
 
 from oracle import core as O
 from synth import make_config, make_frame, ring_cameras
-from synth.scenes import make_camera, _scene_c1, _scene_c2
+from synth.scenes import Primitive, make_camera, _scene_c1, _scene_c2
 from tests.conftest import cached_frame
 from tests.gpu_helpers import compare, oracle_params, run_gpu
 
@@ -148,6 +148,47 @@ def test_identity_fusion(ctx, ff):
     f = make_frame(cams[:1], prims, 1000, noise=False)
     g, o = _case(ctx, ff, f, "identity", ff.Params(level_override=6))
     assert g["n_members"].max() == 1
+
+
+def _border_band_pairs(frame, margin=0.0625):
+    """(point, other camera) pairs whose u + 1/2 or v + 1/2 lies within `margin` px of that
+    camera's image border, in the oracle's float32 arithmetic: the cases the field-of-view
+    test must settle with the exact quotients."""
+    cams = [O.camera_f32(c) for c in frame.cams]
+    pts = O.generate_points(cams, frame.depth, frame.conf, O.Params())
+    F = np.float32
+    n = 0
+    for j, cm in enumerate(cams):
+        p = pts["xyz"][pts["cam"] != j]
+        X = [((cm.R[a, 0] * p[:, 0] + cm.R[a, 1] * p[:, 1]) + cm.R[a, 2] * p[:, 2]) + cm.t[a]
+             for a in range(3)]
+        with np.errstate(all="ignore"):
+            u = cm.fx * (X[0] / X[2]) + cm.cx + F(0.5)
+            v = cm.fy * (X[1] / X[2]) + cm.cy + F(0.5)
+        W, H = F(cm.width), F(cm.height)
+        near_u = (np.abs(u) < margin) | (np.abs(u - W) < margin)
+        near_v = (np.abs(v) < margin) | (np.abs(v - H) < margin)
+        in_u = (u > -margin) & (u < W + margin)
+        in_v = (v > -margin) & (v < H + margin)
+        n += int(((X[2] > 0) & ((near_u & in_v) | (near_v & in_u))).sum())
+    return n
+
+
+def test_field_of_view_border_band(ctx, ff):
+    """A fine camera over a plane and two coarse cameras that each see part of it: the fine
+    camera's points fall densely across the coarse cameras' image borders, so hundreds of
+    representatives lie within 1/16 px of a border (Eq. 4 visibility decided by the exact
+    quotients), and with K - 1 = 2 both other cameras are kept whenever visible, so every
+    such decision changes V."""
+    A = make_camera(160, 120, np.array([0.0, -1.0, 2.0]), np.array([0.0, 0.3, 0.0]))
+    B = make_camera(40, 30, np.array([0.45, -1.2, 2.6]), np.array([0.55, 0.5, 0.0]))
+    C = make_camera(40, 30, np.array([-0.4, -0.8, 2.4]), np.array([-0.5, 0.1, 0.0]))
+    plane = Primitive("plane", np.zeros(3), np.array([0.0, 5.0]), np.array([0.5, 0.5, 0.5]))
+    f = make_frame([A, B, C], [plane], 4242)
+    assert _border_band_pairs(f) >= 150
+    # level 6 everywhere: nearly every point is its own cell's representative
+    g, o = _case(ctx, ff, f, "field-of-view border band", ff.Params(level_override=6))
+    assert (o["reps"] != O.PAD).sum() > 0.9 * len(o["member_ids"])
 
 
 def test_batch_equals_single(ctx, ff):
