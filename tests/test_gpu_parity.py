@@ -3,6 +3,8 @@
 Bit-exact: point counts, cell keys, membership, representative ids.  Within 1e-5
 (relative): fused coordinates and weights.  Every case prints its name before the GPU step.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -189,6 +191,28 @@ def test_field_of_view_border_band(ctx, ff):
     # level 6 everywhere: nearly every point is its own cell's representative
     g, o = _case(ctx, ff, f, "field-of-view border band", ff.Params(level_override=6))
     assert (o["reps"] != O.PAD).sum() > 0.9 * len(o["member_ids"])
+
+
+@pytest.mark.parametrize("steps", [16, 1024])
+def test_quantised_confidences(ctx, ff, steps):
+    """Confidences rounded to multiples of 1/steps: equal confidences among a cell's best
+    three are common (about 81,000 cells of c2 at 1/16, 2,300 at 1/1024), so the ranking
+    must fall back to the full order (position, then pixel id) both in the three-member
+    path and in the four-lanes-per-cell path, and the tie must be detected per member."""
+    f = cached_frame("c2")
+    conf = [(np.round(c.astype(np.float64) * steps) / steps).astype(np.float32) for c in f.conf]
+    g, o = _case(ctx, ff, dataclasses.replace(f, conf=conf), f"c2 confidences in 1/{steps}")
+    # the ties are really there
+    call = np.concatenate([c.ravel() for c in conf])
+    mo, mi = o["member_offsets"], o["member_ids"]
+    n = np.diff(mo)
+    tied = 0
+    for s in np.flatnonzero(n >= 2):
+        cs = np.sort(call[mi[mo[s]:mo[s + 1]]])[::-1]
+        k = min(3, len(cs))
+        if len(np.unique(cs[:k])) < k or (len(cs) > k and cs[k] == cs[k - 1]):
+            tied += 1
+    assert tied >= (50_000 if steps == 16 else 1_000), tied
 
 
 def test_batch_equals_single(ctx, ff):
