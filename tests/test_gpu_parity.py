@@ -193,6 +193,34 @@ def test_field_of_view_border_band(ctx, ff):
     assert (o["reps"] != O.PAD).sum() > 0.9 * len(o["member_ids"])
 
 
+def test_exact_distance_ties_between_views(ctx, ff):
+    """Two cameras mirrored in x about a centre camera whose middle column back-projects to
+    x = 0 exactly: those points are at exactly the same squared distance from both mirrored
+    centres (152 of them visible in both).  With K = 2 one view is kept, so the camera
+    rank (centre x first) decides which, and the scene is asymmetric, so the choice changes
+    V.  Every point is its own cell."""
+    A = make_camera(320, 240, np.array([0.0, -3.0, 0.5]), np.array([0.0, 0.0, 0.0]))
+    B = make_camera(320, 240, np.array([1.5, -2.5, 0.5]), np.array([0.2, 0.0, 0.0]))
+    C = make_camera(320, 240, np.array([-1.5, -2.5, 0.5]), np.array([-0.2, 0.0, 0.0]))
+    rng = np.random.default_rng(77)
+    prims = [Primitive("plane", np.zeros(3), np.array([-1.0, 6.0]), np.array([0.5, 0.5, 0.5]))]
+    for c, r in (([0.35, 0.4, -0.3], 0.45), ([-0.6, 0.9, 0.2], 0.3), ([0.1, -0.5, 0.4], 0.25),
+                 ([0.9, 0.2, 0.6], 0.35)):
+        prims.append(Primitive("sphere", np.array(c), np.array([r]), rng.uniform(0.2, 1, 3)))
+    f = make_frame([A, B, C], prims, 99)
+    # the ties are there: exact equal squared distances, both mirrored cameras in view
+    cams = [O.camera_f32(c) for c in f.cams]
+    pts = O.generate_points(cams, f.depth, f.conf, O.Params())
+    p = pts["xyz"][pts["cam"] == 0]
+
+    def d2(c):
+        return ((p[:, 0] - c[0]) ** 2 + (p[:, 1] - c[1]) ** 2) + (p[:, 2] - c[2]) ** 2
+
+    both = O.project(cams[1], p.T)[0] & O.project(cams[2], p.T)[0]
+    assert int(((d2(cams[1].centre) == d2(cams[2].centre)) & both).sum()) >= 100
+    _case(ctx, ff, f, "exact distance ties", ff.Params(k_views=2, level_override=6))
+
+
 @pytest.mark.parametrize("steps", [16, 1024])
 def test_quantised_confidences(ctx, ff, steps):
     """Confidences rounded to multiples of 1/steps: equal confidences among a cell's best
