@@ -221,6 +221,22 @@ def test_exact_distance_ties_between_views(ctx, ff):
     _case(ctx, ff, f, "exact distance ties", ff.Params(k_views=2, level_override=6))
 
 
+def test_duplicate_cameras(ctx, ff):
+    """c1 with its first camera twice (same pose, depth, confidence and colour): every point
+    of that camera has an exact twin, so cells hold members equal in confidence and
+    position and the full order falls through to the pixel id; the twin cameras' ranks
+    tie on the centre and fall to the index; and a twin is always the nearest other view,
+    where its depth reprojects the point exactly."""
+    f = cached_frame("c1")
+    g = dataclasses.replace(f, cams=[f.cams[0], f.cams[0], f.cams[1]],
+                            depth=[f.depth[0], f.depth[0].copy(), f.depth[1]],
+                            conf=[f.conf[0], f.conf[0].copy(), f.conf[1]],
+                            rgb=[f.rgb[0], f.rgb[0].copy(), f.rgb[1]])
+    for level in (None, 6):
+        prm = ff.Params() if level is None else ff.Params(level_override=level)
+        _case(ctx, ff, g, f"c1 with a duplicated camera, level {level}", prm)
+
+
 @pytest.mark.parametrize("steps", [16, 1024])
 def test_quantised_confidences(ctx, ff, steps):
     """Confidences rounded to multiples of 1/steps: equal confidences among a cell's best
