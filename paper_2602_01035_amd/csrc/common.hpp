@@ -99,7 +99,8 @@ struct CallHdr {
     uint32_t n_cell_items, max_radix_bits;
     uint32_t npass_max, n_counts;
     uint32_t sort_items, lds_cams;
-    uint32_t any_mids, pad_;
+    uint32_t any_mids;
+    uint32_t key64_ok;               // the key-width bound allows keys wider than 32 bits
 };
 
 // per pixel tile: AABB partial (order-preserving encodings) and gated count

@@ -140,21 +140,23 @@ int ilog2(uint32_t v) {
 
 // scatter staging: keys (u64 worst case) and ids of a tile, per-wave and per-tile digit
 // counters for the configured digit width, the cameras' pixel offsets
-size_t down_smem(int items, int bits, uint32_t ncams) {
+size_t down_smem(int items, int bits, uint32_t ncams, bool key64 = true) {
     const size_t kt = (size_t)kBlock * items;
-    return kt * 8 + kt * 4 + (4 + 2) * ((size_t)1 << bits) * 4 + 32 + (size_t)ncams * 4;
+    return kt * (key64 ? 8 : 4) + kt * 4 + (4 + 2) * ((size_t)1 << bits) * 4 + 32 +
+           (size_t)ncams * 4;
 }
 size_t cells_smem(uint32_t ncams, uint32_t nframes) {
     return cells_layout(ncams, ncams <= (uint32_t)kLdsCams, nframes).total;
 }
-size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits, uint32_t nframes) {
+size_t smem_for(uint32_t kind, int items, uint32_t ncams, int bits, uint32_t nframes,
+                bool key64) {
     switch (kind) {
         case PH_BACKPROJECT: return 4 * 8 * 4;
         case PH_TILE_REDUCE: return (8 + 32) * 4;
         case PH_HIST: return kHashSlots * 8;
         case PH_RADIX_UP: return ((size_t)1 << bits) * 4;
         case PH_RADIX_SCAN: return 16 * 4;
-        case PH_RADIX_DOWN: return down_smem(items, bits, ncams);
+        case PH_RADIX_DOWN: return down_smem(items, bits, ncams, key64);
         case PH_HEAD_WRITE: return kMaxFrames * 8 + 16;
         case PH_CELLS: return cells_smem(ncams, nframes);
         case PH_FINAL: return 16;
@@ -382,6 +384,7 @@ struct Plan {
     size_t desc_used = 0;       // bytes of the descriptor this call fills
     int radix_bits = 10;        // widest digit of the sort passes
     uint32_t nframes = 0;
+    bool key64_ok = true;       // the key-width bound allows 64-bit keys (scatter LDS size)
 };
 
 // Validate one batch and fill the host staging descriptor.  Returns the launch plan and a
@@ -523,6 +526,10 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
         }
         const uint32_t bits_max = bound > 1 ? (uint32_t)(64 - __builtin_clzll(bound - 1)) : 0u;
         H->npass_max = std::max<uint32_t>(1, (bits_max + H->max_radix_bits - 1) / H->max_radix_bits);
+        // keys stay 32-bit on the device whenever the bound allows no more: the scatter
+        // then stages 4-byte keys and more of its workgroups fit per CU
+        H->key64_ok = bits_max > 32 ? 1u : 0u;
+        plan.key64_ok = bits_max > 32;
     }
     if (H->npass_max > (uint32_t)kMaxPass) return FF_ERR_INVALID_ARG;
     plan.launches.clear();
@@ -553,9 +560,12 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     add(PH_FINAL, 1, 0);
     char tail[96];
     // everything the captured launches depend on besides the per-camera sizes above: grid
-    // and level limits, flags, the per-cell kernel variant, tuning
-    std::snprintf(tail, sizeof(tail), "|G%d|L%d|f%u|w%d|t%d,%d", G, prm->max_level, prm->flags,
-                  plan.wide_views ? 1 : 0, c->tune.radix_bits, c->tune.sort_items);
+    // and level limits, flags, the per-cell kernel variant, tuning, and the sort's pass
+    // count and key width (set by the level limits and the target count through the
+    // key-width bound; the key width sizes the scatter's LDS)
+    std::snprintf(tail, sizeof(tail), "|G%d|L%d|f%u|w%d|t%d,%d|p%u,%u", G, prm->max_level,
+                  prm->flags, plan.wide_views ? 1 : 0, c->tune.radix_bits, c->tune.sort_items,
+                  H->npass_max, H->key64_ok);
     shape += tail;
     return FF_OK;
 }
@@ -660,7 +670,8 @@ void launch_cells(const Ctx& C, uint32_t ncams, const Plan& plan, hipStream_t s,
 
 template <int ITEMS>
 void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, const Plan& plan, hipStream_t s) {
-    const size_t smem = smem_for(L.kind, ITEMS, ncams, plan.radix_bits, plan.nframes);
+    const size_t smem =
+        smem_for(L.kind, ITEMS, ncams, plan.radix_bits, plan.nframes, plan.key64_ok);
     const dim3 grid(std::max<uint32_t>(1, L.n)), block(kBlock);
 #define FF_L(K) hipLaunchKernelGGL((k_phase<K, ITEMS>), grid, block, smem, s, C, L.pass)
     switch (L.kind) {

@@ -877,7 +877,11 @@ __device__ __forceinline__ void ph_scan_m(const Ctx& C, uint32_t, char* smem) {
     if (threadIdx.x == 0) {
         BatchState& bs = *C.bs;
         bs.T_tot = carry;
-        const uint32_t bits = carry > 1 ? 64u - (uint32_t)__clzll((long long)(carry - 1)) : 0u;
+        uint32_t bits = carry > 1 ? 64u - (uint32_t)__clzll((long long)(carry - 1)) : 0u;
+        if (bits > 32u && !H.key64_ok) {   // cannot happen: the bound fixed 32-bit keys (and
+            raise_error(C.bs, kErrBounds); // the scatter's staging size); stay within it
+            bits = 32u;
+        }
         bs.key_bits = bits;
         bs.key64 = bits > 32 ? 1u : 0u;
         const uint32_t mb = H.max_radix_bits;

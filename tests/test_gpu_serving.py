@@ -68,6 +68,28 @@ def test_graph_replay_follows_view_budget(ff):
     ctx.close()
 
 
+def test_graph_replay_follows_key_width(ff):
+    """The same batch shape with level limits that change the sort's pass count and key
+    width (the scatter's LDS holds 4- or 8-byte keys by the host's key-width bound) must
+    not replay a graph captured for other ones.  Level 12 everywhere on one coarse cell
+    needs 36-bit keys, so the 64-bit path runs too; every result against the oracle."""
+    print("[case] graph replay across key widths", flush=True)
+    f = cached_frame("c2")
+    devs = [ff.to_device(f)]
+    ctx = ff.Context(max_pixels=2_000_000, max_cameras=8, max_frames=2)
+    wide = dict(coarse_res=1, max_level=12, level_override=12)
+    for kw in (dict(), wide, dict(), dict(max_level=10, target_per_cell=1),
+               dict(level_override=0), wide):
+        p = ff.Params(**kw)
+        g = ctx.fuse_batch(devs, params=p)[0].result()
+        compare(g, O.fuse_frame(f, oracle_params(p)), label=f"batched {kw}")
+    p = ff.Params(**wide)
+    d = devs[0]
+    g = ctx.fuse(d["cams"], d["depth"], d["conf"], d.get("rgb"), params=p).result()
+    compare(g, O.fuse_frame(f, oracle_params(p)), check_members=False, label="plain, 36-bit keys")
+    ctx.close()
+
+
 @pytest.mark.parametrize("tuning", [dict(radix_bits=6, sort_items=8),
                                     dict(radix_bits=8, sort_items=16),
                                     dict(radix_bits=10, sort_items=8)])
