@@ -74,9 +74,9 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # sources they were taken on (their digest); otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "a1a5ff6e235e17ed",
-    "fetch_kib_per_frame": 87643.7,
-    "write_kib_per_frame": 54229.0,
+    "source_digest": "599a6c44e4133ecb",
+    "fetch_kib_per_frame": 87658.7,
+    "write_kib_per_frame": 54229.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
