@@ -10,7 +10,7 @@ import pytest
 
 from oracle import core as O
 from synth import make_config, make_frame, ring_cameras
-from synth.scenes import Primitive, make_camera, _scene_c1, _scene_c2
+from synth.scenes import Camera, Primitive, make_camera, _scene_c1, _scene_c2
 from tests.conftest import cached_frame
 from tests.gpu_helpers import compare, oracle_params, run_gpu
 
@@ -191,6 +191,33 @@ def test_field_of_view_border_band(ctx, ff):
     # level 6 everywhere: nearly every point is its own cell's representative
     g, o = _case(ctx, ff, f, "field-of-view border band", ff.Params(level_override=6))
     assert (o["reps"] != O.PAD).sum() > 0.9 * len(o["member_ids"])
+
+
+def test_cameras_at_the_range_limits(ctx, ff):
+    """Cameras at the limits the boundary admits: a 16384 x 1 strip, a 1 x 4000 strip,
+    |f| = 2^20 with the principal point at -16000 (a sliver of view, u far from the
+    principal point) and |f| = 2^-20 (a near-hemispherical view), beside an ordinary
+    camera.  Tiles, pixel coordinates and the field-of-view fast path at its error bound
+    must all agree with the oracle."""
+    def strip(base, w, h, fx, cx, cy):
+        return Camera(w, h, float(fx), float(fx), float(cx), float(cy), base.world_to_cam)
+
+    c0 = make_camera(320, 240, np.array([0.0, -3.0, 0.6]), np.array([0.0, 0.0, 0.0]))
+    b1 = make_camera(8, 8, np.array([2.5, -1.5, 0.4]), np.array([0.1, 0.1, 0.0]))
+    b2 = make_camera(8, 8, np.array([-2.2, -1.8, 0.8]), np.array([-0.1, 0.2, 0.1]))
+    b3 = make_camera(8, 8, np.array([0.3, 2.8, 0.5]), np.array([0.0, -0.1, 0.0]))
+    b4 = make_camera(8, 8, np.array([-2.0, 2.0, 1.2]), np.array([0.0, 0.0, -0.2]))
+    cams = [c0, strip(b1, 16384, 1, 4000.0, 8192.0, 0.5), strip(b2, 1, 4000, 300.0, 0.5, 2000.0),
+            strip(b3, 64, 48, 2.0 ** 20, -16000.0, 24.0), strip(b4, 40, 30, 2.0 ** -20, 20.0, 15.0)]
+    rng = np.random.default_rng(5)
+    prims = [Primitive("plane", np.zeros(3), np.array([-1.0, 8.0]), np.array([0.5, 0.5, 0.5]))]
+    for c, r in (([0.3, 0.2, -0.4], 0.5), ([-0.5, 0.6, 0.1], 0.35), ([0.6, -0.4, 0.3], 0.3)):
+        prims.append(Primitive("sphere", np.array(c), np.array([r]), rng.uniform(0.2, 1, 3)))
+    f = make_frame(cams, prims, 31)
+    pts = O.generate_points([O.camera_f32(c) for c in f.cams], f.depth, f.conf, O.Params())
+    assert np.all(np.bincount(pts["cam"], minlength=len(cams)) > 100)   # every camera counts
+    for prm in (ff.Params(), ff.Params(level_override=6), ff.Params(k_views=5)):
+        _case(ctx, ff, f, "cameras at the range limits", prm)
 
 
 def test_exact_distance_ties_between_views(ctx, ff):
