@@ -190,10 +190,12 @@ __device__ __forceinline__ bool finite3(const Pt& p) {
 // far more than the error.  The ranges are tested as med3(t, lo, hi) == t, which holds
 // exactly when lo <= t <= hi and never for a NaN t; the upper ends are the largest floats
 // below W - m (clearly inside) and W + m (not clearly outside), so the tests are the
-// half-open intervals.  "Clearly outside" also needs both approximations to be numbers: an
-// approximation that is not a number (0 times the infinite reciprocal of a subnormal Z) is
-// never clearly anything and goes to the exact quotients.  Written without early exits:
-// only the rare border case branches.
+// half-open intervals.  The bound needs an accurate reciprocal, so unless the approximate
+// reciprocal is a positive normal float (a subnormal Z has an infinite one, and X times it
+// may be infinite while X/Z is small; above 2^126 the reciprocal is subnormal and may be
+// flushed to 0) the point is never clearly anything, and neither is an approximation that
+// is not a number; both go to the exact quotients.  Written without early exits: only the
+// rare border case branches.
 constexpr float kFovMargin = 0.0625f;
 template <typename Cam>
 __device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p) {
@@ -205,11 +207,14 @@ __device__ __forceinline__ bool in_view_fast(const Cam& cm, const Pt& p) {
     const float tb = __builtin_fmaf(cm.fy, Y * rz, cm.cyh);
     const float m = kFovMargin;
     const bool front = Z > 0.0f;
-    const bool sure_in = (__builtin_amdgcn_fmed3f(ta, m, cm.in_hx) == ta) &
+    // the approximate reciprocal is a positive normal float: Z > 0, not subnormal (whose
+    // reciprocal is infinite or flushed) and below 2^126 (whose reciprocal is subnormal)
+    const bool normal_z = __builtin_amdgcn_classf(rz, 1 << 8);
+    const bool sure_in = normal_z & (__builtin_amdgcn_fmed3f(ta, m, cm.in_hx) == ta) &
                          (__builtin_amdgcn_fmed3f(tb, m, cm.in_hy) == tb);
     const bool near = (__builtin_amdgcn_fmed3f(ta, -m, cm.out_hx) == ta) &
                       (__builtin_amdgcn_fmed3f(tb, -m, cm.out_hy) == tb);
-    const bool sure_out = !near & !__builtin_isunordered(ta, tb);
+    const bool sure_out = normal_z & !near & !__builtin_isunordered(ta, tb);
     bool in = front & sure_in;
     if (front & !sure_in & !sure_out) {
         const float W = (float)cm.W, H = (float)cm.H;

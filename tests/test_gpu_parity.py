@@ -220,6 +220,40 @@ def test_cameras_at_the_range_limits(ctx, ff):
         _case(ctx, ff, f, "cameras at the range limits", prm)
 
 
+@pytest.mark.parametrize("kind", ["subnormal", "huge"])
+def test_extreme_depths(ctx, ff, kind):
+    """Two cameras at the world origin (t = 0 exactly) and a third elsewhere.  "subnormal":
+    blocks of subnormal depths (down to the smallest one) give points within 1e-38 of the
+    origin, equal in confidence, so their cell is ranked on subnormal positions, and their
+    camera-frame Z in the other origin camera is subnormal (the approximate reciprocal is
+    infinite and the exact quotients decide).  "huge": depths of 1e30 give points near
+    1e30 (the coarse exponent clamps) and 3e38 overflows when back-projected (gated out)."""
+    A = make_camera(160, 120, np.array([0.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.1]))
+    B = make_camera(160, 120, np.array([0.0, 0.0, 0.0]), np.array([0.4, 1.0, 0.0]))
+    C = make_camera(160, 120, np.array([0.0, -1.5, 0.4]), np.array([0.0, 1.0, 0.0]))
+    rng = np.random.default_rng(8)
+    prims = [Primitive("plane", np.zeros(3), np.array([-1.0, 8.0]), np.array([0.5, 0.5, 0.5]))]
+    for c, r in (([0.0, 2.0, 0.0], 0.5), ([0.6, 2.5, 0.3], 0.4), ([-0.5, 1.8, -0.2], 0.3)):
+        prims.append(Primitive("sphere", np.array(c), np.array([r]), rng.uniform(0.2, 1, 3)))
+    f = make_frame([A, B, C], prims, 12)
+    d0, c0 = f.depth[0].copy(), f.conf[0].copy()
+    d1, c1 = f.depth[1].copy(), f.conf[1].copy()
+    if kind == "subnormal":
+        sub = np.float32(1e-39) * np.arange(1, 11, dtype=np.float32)
+        d0[40:50, 60:100] = np.resize(sub, (10, 40))
+        c0[40:50, 60:100] = 0.9
+        d1[70:75, 70:90] = np.float32(1.4e-45)
+        c1[70:75, 70:90] = 0.8
+    else:
+        d0[60:62, 10:20] = np.float32(1e30)
+        c0[60:62, 10:20] = 0.95
+        d0[62, 10:20] = np.float32(3e38)
+        c0[62, 10:20] = 0.95
+    g = dataclasses.replace(f, depth=[d0, d1, f.depth[2]], conf=[c0, c1, f.conf[2]])
+    for prm in (ff.Params(), ff.Params(level_override=6)):
+        _case(ctx, ff, g, f"{kind} depths", prm)
+
+
 def test_exact_distance_ties_between_views(ctx, ff):
     """Two cameras mirrored in x about a centre camera whose middle column back-projects to
     x = 0 exactly: those points are at exactly the same squared distance from both mirrored
