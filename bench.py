@@ -74,9 +74,9 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # sources they were taken on (their digest); otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "599a6c44e4133ecb",
-    "fetch_kib_per_frame": 87658.7,
-    "write_kib_per_frame": 54229.4,
+    "source_digest": "af7b4c2175c63231",
+    "fetch_kib_per_frame": 87713.6,
+    "write_kib_per_frame": 54241.1,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
