@@ -42,12 +42,20 @@ def compare(g, o, check_members=True, label=""):
         assert np.array_equal(g["member_offsets"], o["member_offsets"]), (label, "offsets")
         assert np.array_equal(g["member_ids"], o["member_ids"]), (label, "member ids")
     if S:
-        scale = np.maximum(np.abs(o["xyz"]).max(axis=1), 1.0)
-        err = np.abs(g["xyz"].astype(np.float64) - o["xyz"]).max(axis=1)
+        gx, ox = g["xyz"].astype(np.float64), np.asarray(o["xyz"], np.float64)
+        gw, ow = g["weight"].astype(np.float64), np.asarray(o["weight"], np.float64)
+        # a NaN on one side only is a mismatch (a comparison with NaN is never "too far")
+        assert np.array_equal(np.isnan(gx), np.isnan(ox)), (label, "xyz NaN positions")
+        assert np.array_equal(np.isnan(gw), np.isnan(ow)), (label, "weight NaN positions")
+        assert np.array_equal(np.isinf(gx), np.isinf(ox)), (label, "xyz inf positions")
+        fin = np.isfinite(ox)
+        scale = np.maximum(np.abs(np.where(fin, ox, 0.0)).max(axis=1), 1.0)
+        err = np.where(fin, np.abs(gx - np.where(fin, ox, 0.0)), 0.0).max(axis=1)
         bad = np.flatnonzero(err > XYZ_RTOL * scale)
         assert len(bad) == 0, (label, "xyz", bad[:5], err[bad[:5]])
-        werr = np.abs(g["weight"].astype(np.float64) - o["weight"])
-        wbad = np.flatnonzero(werr > W_RTOL * np.maximum(o["weight"], 1e-6))
+        wfin = np.isfinite(ow)
+        werr = np.where(wfin, np.abs(gw - np.where(wfin, ow, 0.0)), 0.0)
+        wbad = np.flatnonzero(werr > W_RTOL * np.maximum(np.where(wfin, ow, 0.0), 1e-6))
         assert len(wbad) == 0, (label, "weight", wbad[:5], g["weight"][wbad[:5]],
                                 o["weight"][wbad[:5]])
         if o.get("rgb") is not None and g.get("rgb") is not None:
