@@ -79,6 +79,47 @@ def test_random_small_rigs(ctx, ff, seed):
     _case(ctx, ff, f, f"random rig {seed} {res}")
 
 
+def _admissible_extremes_frame(seed):
+    """A small rig with half of its cameras given intrinsics drawn across the whole range
+    the boundary admits (|f| log-uniform in [2^-20, 2^20], either sign, principal point off
+    the image), and random blocks of subnormal, tiny or far depths."""
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(2, 6))
+    res = [(int(rng.integers(1, 300)), int(rng.integers(1, 300))) for _ in range(n)]
+    base = ring_cameras(res, radius=float(rng.uniform(1.5, 4.0)), jitter_pos=0.4,
+                        jitter_target=0.5, rng=rng)
+    cams = []
+    for (w, h), b in zip(res, base):
+        if rng.random() < 0.5:
+            e = rng.uniform(-20, 20)
+            fx = float(2.0 ** e) * (1 if rng.random() < 0.8 else -1)
+            fy = float(2.0 ** float(np.clip(e + rng.uniform(-2, 2), -20, 20)))
+            cx = float(np.clip(rng.uniform(-2 * w, 3 * w), -16384, 16384))
+            cy = float(np.clip(rng.uniform(-2 * h, 3 * h), -16384, 16384))
+            cams.append(Camera(w, h, fx, fy, cx, cy, b.world_to_cam))
+        else:
+            cams.append(b)
+    prims = _scene_c2(rng, base)
+    fr = make_frame(cams, prims, 7000 + seed, outlier_frac=0.03, conf_model="beta")
+    D = [d.copy() for d in fr.depth]
+    C = [c.copy() for c in fr.conf]
+    for d, c in zip(D, C):
+        for _ in range(int(rng.integers(0, 3))):
+            H, W = d.shape
+            y0, x0 = int(rng.integers(0, H)), int(rng.integers(0, W))
+            d[y0:y0 + 3, x0:x0 + 5] = np.float32(rng.choice([1e-39, 1.4e-45, 3e-30, 40.0]))
+            c[y0:y0 + 3, x0:x0 + 5] = np.float32(rng.uniform(0.61, 1.0))
+    return dataclasses.replace(fr, depth=D, conf=C)
+
+
+@pytest.mark.parametrize("seed", range(64))
+def test_admissible_extremes(ctx, ff, seed):
+    f = _admissible_extremes_frame(seed)
+    desc = [(c.width, c.height, f"{c.fx:.3g}") for c in f.cams]
+    for prm in (ff.Params(), ff.Params(level_override=6)):
+        _case(ctx, ff, f, f"admissible extremes {seed} {desc}", prm)
+
+
 @pytest.mark.parametrize("n_cams,res", [(9, (160, 120)), (12, (128, 96)), (20, (96, 64))])
 def test_frames_with_many_cameras(ctx, ff, n_cams, res):
     """More than 8 cameras in a frame: every camera is tested for the local views."""
