@@ -120,6 +120,17 @@ def test_admissible_extremes(ctx, ff, seed):
         _case(ctx, ff, f, f"admissible extremes {seed} {desc}", prm)
 
 
+@pytest.mark.parametrize("first", [0, 8, 16, 24])
+def test_admissible_extremes_batched(ctx, ff, first):
+    """Eight of those rigs in one batched call: frames of very different extents, levels
+    and camera counts share every launch, and each must equal its own oracle result."""
+    frames = [_admissible_extremes_frame(seed) for seed in range(first, first + 8)]
+    print(f"[case] admissible extremes batched {first}..{first + 7}", flush=True)
+    outs = ctx.fuse_batch([ff.to_device(f) for f in frames], members=True)
+    for k, (f, out) in enumerate(zip(frames, outs)):
+        compare(out.result(), O.fuse_frame(f), label=f"batched extremes frame {first + k}")
+
+
 @pytest.mark.parametrize("n_cams,res", [(9, (160, 120)), (12, (128, 96)), (20, (96, 64))])
 def test_frames_with_many_cameras(ctx, ff, n_cams, res):
     """More than 8 cameras in a frame: every camera is tested for the local views."""
