@@ -131,6 +131,32 @@ def test_admissible_extremes_batched(ctx, ff, first):
         compare(out.result(), O.fuse_frame(f), label=f"batched extremes frame {first + k}")
 
 
+def _random_params(ff, seed):
+    """Parameters drawn across the ranges the library admits (coarse_res a power of two up
+    to 128 and K up to 8, as its header states; level limits, target count, sigma, tau and
+    ablation flags over the method's ranges)."""
+    rng = np.random.default_rng(6000 + seed)
+    lg = int(rng.integers(0, 8))                          # coarse_res 1 .. 128
+    lmax = int(rng.integers(0, min(16, 56 // 3 - lg) + 1))
+    lo = -1 if rng.random() < 0.7 else int(rng.integers(0, lmax + 1))
+    flags = int(rng.choice([0, 0, 0, 1, 2, 3, 4]))
+    return ff.Params(coarse_res=1 << lg, max_level=lmax, level_override=lo,
+                     target_per_cell=int(rng.integers(1, 65)), k_views=int(rng.integers(1, 9)),
+                     sigma=float(10.0 ** rng.uniform(-4, 0)), tau=float(rng.uniform(0.0, 0.95)),
+                     flags=flags)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_parameters(ctx, ff, seed):
+    f = cached_frame("c1")
+    p = _random_params(ff, seed)
+    label = (f"random parameters {seed}: G {p.coarse_res} Lmax {p.max_level} "
+             f"override {p.level_override} target {p.target_per_cell} K {p.k_views} "
+             f"flags {p.flags}")
+    _case(ctx, ff, f, label, p)
+    _case(ctx, ff, f, label + " batched", p, batch=True)
+
+
 @pytest.mark.parametrize("n_cams,res", [(9, (160, 120)), (12, (128, 96)), (20, (96, 64))])
 def test_frames_with_many_cameras(ctx, ff, n_cams, res):
     """More than 8 cameras in a frame: every camera is tested for the local views."""
@@ -442,6 +468,8 @@ def test_bad_arguments_raise(ctx, ff):
         ctx.fuse(dev["cams"], dev["depth"], dev["conf"], params=ff.Params(coarse_res=48))
     with pytest.raises(ff.FuseFlowError):
         ctx.fuse(dev["cams"], dev["depth"], dev["conf"], params=ff.Params(k_views=9))
+    with pytest.raises(ff.FuseFlowError):     # above the library's coarse grid limit (128)
+        ctx.fuse(dev["cams"], dev["depth"], dev["conf"], params=ff.Params(coarse_res=256))
     small = ff.Context(max_pixels=1000, max_cameras=2)
     with pytest.raises(ff.FuseFlowError):
         small.fuse(dev["cams"], dev["depth"], dev["conf"])
