@@ -157,6 +157,14 @@ def test_random_parameters(ctx, ff, seed):
     _case(ctx, ff, f, label + " batched", p, batch=True)
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_admissible_extremes_random_parameters(ctx, ff, seed):
+    """The extreme-intrinsics rigs under random parameter sets."""
+    f = _admissible_extremes_frame(100 + seed)
+    p = _random_params(ff, 100 + seed)
+    _case(ctx, ff, f, f"extremes {100 + seed} with random parameters {100 + seed}", p)
+
+
 @pytest.mark.parametrize("n_cams,res", [(9, (160, 120)), (12, (128, 96)), (20, (96, 64))])
 def test_frames_with_many_cameras(ctx, ff, n_cams, res):
     """More than 8 cameras in a frame: every camera is tested for the local views."""
