@@ -362,6 +362,46 @@ def test_fusion_closed_forms():
     assert w[2] == pytest.approx((0.8 + 0.8 / 3) / 2, rel=1e-7)
 
 
+def test_fusion_colour_closed_forms():
+    """Eq. 11 applied to colour: rint of the same normalised weights pi_r = w_r / sum w,
+    w_r = C_r V_r (Eq. 10), clamped to [0, 255].  Each case is worked by hand, and chosen so
+    that a plausible slip gives another value: raw weights w instead of pi, confidence
+    without V, truncation instead of rounding, or rounding half away from zero."""
+    n = 12
+    xyz = np.zeros((n, 3), F32)
+    conf = np.array([0.8, 0.4, 0.8, 0.8, 0.9, 0.6, 0.3, 0.5, 0.5, 0.5, 0.5, 0.7], F32)
+    rgb = np.array([[30, 0, 101], [60, 255, 100],        # cell 0: pi = 2/3, 1/3
+                    [40, 7, 200], [80, 11, 0],           # cell 1: pi = 3/4, 1/4
+                    [0, 8, 200], [100, 8, 100], [255, 8, 0],   # cell 2: 1/4, 1/2, 1/4
+                    [10, 11, 254], [11, 12, 255],        # cell 3: 1/2, 1/2 (ties to even)
+                    [255, 255, 255], [255, 255, 255],    # cell 4: the top of the range
+                    [7, 8, 9]], np.uint8)                # cell 5: one representative
+    pts = dict(xyz=xyz, conf=conf, pix=np.arange(n))
+    reps = np.array([[0, 1, -1], [2, 3, -1], [4, 5, 6], [7, 8, -1], [9, 10, -1],
+                     [11, -1, -1]])
+    ln3 = math.log(3.0)
+    expo = np.array([[0, 0, 0], [0, ln3, 0], [ln3, 0, 0], [0, 0, 0], [0.25, 0.25, 0],
+                     [40.0, 0, 0]], np.float64)
+    _, w, col = O.fuse_cells(reps, expo, pts, rgb)
+    expect = np.array([
+        # 2/3 (30, 0, 101) + 1/3 (60, 255, 100) = (40, 85, 100.67) -> (40, 85, 101)
+        # (raw weights 0.8, 0.4 would give 48; truncation would give 100 in blue)
+        [40, 85, 101],
+        # w = (0.8, 0.8/3): 3/4 (40, 7, 200) + 1/4 (80, 11, 0) = (50, 8, 150)
+        # (C alone would give pi = 1/2: 60 in red)
+        [50, 8, 150],
+        # w = (0.3, 0.6, 0.3): (0 + 50 + 63.75, 8, 50 + 50) -> (114, 8, 100)
+        [114, 8, 100],
+        # halves round to even: (10.5, 11.5, 254.5) -> (10, 12, 254)
+        [10, 12, 254],
+        [255, 255, 255],
+        [7, 8, 9]], np.uint8)
+    assert (col == expect).all(), col
+    assert w[0] == pytest.approx((0.8 + 0.4) / 2, rel=1e-7)
+    assert w[2] == pytest.approx(0.4, rel=1e-6)
+    assert w[5] == pytest.approx(0.7 * math.exp(-40.0), rel=1e-6)
+
+
 def test_fusion_convexity(frame_c2):
     r = O.fuse_frame(frame_c2, debug=True)
     d = r["debug"]
@@ -475,6 +515,8 @@ def test_empty_and_degenerate_frames():
 
 
 def _bad_cameras(cam):
+    """Cameras the library rejects: non-finite parameters, and (its own limits) focal
+    lengths outside [2^-20, 2^20] px and a principal point beyond +-16384 px."""
     import dataclasses
     T = cam.world_to_cam.copy()
     T[1, 3] = np.inf
@@ -485,18 +527,31 @@ def _bad_cameras(cam):
 
 
 def test_camera_validation():
+    """The oracle rejects only what the method cannot use: non-finite parameters and empty
+    images.  Focal lengths and principal points of any finite value are accepted."""
     import dataclasses
     cam = make_camera(4, 4, np.array([0.0, -3, 0]), np.zeros(3))
     D = [np.ones((4, 4), F32)]
     C = [np.ones((4, 4), F32)]
-    for bad in _bad_cameras(cam):
+    T = cam.world_to_cam.copy()
+    T[1, 3] = np.inf
+    for bad in (dataclasses.replace(cam, fx=np.nan), dataclasses.replace(cam, cy=-np.inf),
+                dataclasses.replace(cam, world_to_cam=T)):
         with pytest.raises(ValueError):
             O.fuse([bad], D, C)
-    with pytest.raises(ValueError):
-        O.validate_camera(dataclasses.replace(cam, width=16385))
-    # the edges of the admitted range are accepted
-    O.fuse([dataclasses.replace(cam, fx=2.0 ** 20, fy=-(2.0 ** -20), cx=16384.0, cy=-16384.0)],
-           D, C)
+    for bad in (dataclasses.replace(cam, width=0), dataclasses.replace(cam, height=-1)):
+        with pytest.raises(ValueError):
+            O.validate_camera(bad)
+    # finite parameters far outside any implementation range are the method's business
+    for ok in (dataclasses.replace(cam, fx=2.0 ** 30, fy=-(2.0 ** -30), cx=1e6, cy=-1e6),
+               dataclasses.replace(cam, fx=0.0)):
+        r = O.fuse([ok], D, C)
+        assert r["weight"].dtype == np.float32
+    # a zero focal length sends every ray to (x - cx)/0, infinite or (at x = cx) 0/0:
+    # no point is finite, so all are dropped
+    z = dataclasses.replace(cam, fx=0.0, cx=2.0, cy=2.0)
+    r = O.fuse([z], D, C, debug=True)
+    assert r["debug"]["M"] == 0 and len(r["keys"]) == 0
 
 
 def test_parameter_validation():
