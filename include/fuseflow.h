@@ -41,6 +41,7 @@
  *     HIP errors).  Data-dependent outcomes are written to device memory: *count receives
  *     the number of fused points S; if S > capacity only the first `capacity` points are
  *     written and *status becomes FF_DEV_OVERFLOW.  capacity >= sum(W*H) never overflows.
+ *     FF_DEV_ERROR in *status reports a failed internal bounds check (see the enum).
  *   - Pixel ids are frame-global: camera-major (cameras in the order given), then y*W + x.
  *     A frame must have fewer than 2^32 pixels.
  *   - A context is not thread-safe: calls on one context must not overlap from several
@@ -77,7 +78,14 @@ enum {
 };
 
 /* values of *ff_output.status */
-enum { FF_DEV_OK = 0, FF_DEV_OVERFLOW = 1 };
+enum {
+    FF_DEV_OK = 0,
+    FF_DEV_OVERFLOW = 1,   /* S > capacity (or M > member_capacity): output truncated */
+    FF_DEV_ERROR = 2       /* an internal consistency check of the device path failed (an
+                              index out of its bounds); raised for every frame of the call
+                              that found it, since the frames of a call share the
+                              workspace.  Outputs of that call are unreliable. */
+};
 
 /* Fusion calls reject (FF_ERR_INVALID_ARG) a camera with a non-finite parameter, a side
  * above 16384 px, a principal point beyond +-16384 px or a focal length outside
@@ -122,7 +130,7 @@ typedef struct ff_output {
     uint32_t capacity;            /* entries available in the per-point arrays */
     uint32_t member_capacity;     /* entries available in member_ids */
     uint32_t* count;              /* device [1]: S, the number of fused points */
-    int32_t* status;              /* device [1]: FF_DEV_OK or FF_DEV_OVERFLOW */
+    int32_t* status;              /* device [1]: FF_DEV_OK, FF_DEV_OVERFLOW or FF_DEV_ERROR */
     uint32_t* info;               /* device [4] or NULL: M (gated points), S, R
                                      (representatives), sort key bits */
 } ff_output;
@@ -306,16 +314,27 @@ uint64_t ff_server_lane_pixels(const ff_server* s);
 double ff_server_now(const ff_server* s);
 
 /* Queue one frame of rig `rig_id` arriving at `arrival_s` on the server clock (a time in the
- * past means now).  The host structs are copied; the device images and `out` buffers must
- * stay valid until the frame is done.  FF_ERR_BUSY when max_pending frames wait already. */
+ * past, e.g. a negative one, means the moment of this call).  An event is recorded on
+ * `stream` (the caller's stream, NULL = the null stream) and the frame's batch waits for
+ * it, so work queued there before the submit (writing the images, clearing the outputs)
+ * is complete before the frame is read.  The host structs are copied; the device images
+ * and `out` buffers must stay valid until the frame is done.  Returns, for this frame
+ * only: FF_ERR_INVALID_ARG when the host checks of ff_fuse_batch reject it, FF_ERR_OOM
+ * when it is larger than a lane, FF_ERR_BUSY when max_pending frames wait already.
+ * Nothing about one frame affects the acceptance of other frames. */
 ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
                            const ff_params* params, const ff_output* out, double arrival_s,
-                           uint64_t* ticket);
+                           void* stream, uint64_t* ticket);
 
-/* done = 1 once the frame's results are in its output buffers. */
+/* done = 1 once the frame's results are in its output buffers (its batch's device work has
+ * finished).  Once done is reported, the call returns the frame's own status (FF_OK, or the
+ * error its batch's launch met) and forgets the ticket: a later poll or wait on it returns
+ * FF_ERR_NOT_FOUND. */
 ff_status ff_server_poll(ff_server* s, uint64_t ticket, int32_t* done);
+/* Block until the frame is done; returns its status and forgets the ticket. */
 ff_status ff_server_wait(ff_server* s, uint64_t ticket);
-/* Wait until every submitted frame is done. */
+/* Wait until every submitted frame is done and forget all tickets.  Returns FF_OK, or the
+ * first error a frame completed with since the previous drain. */
 ff_status ff_server_drain(ff_server* s);
 
 ff_status ff_server_stats(const ff_server* s, ff_stats* st);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfuseflow.so")
 
 FF_OK, FF_ERR_INVALID_ARG, FF_ERR_OOM, FF_ERR_BUSY, FF_ERR_HIP, FF_ERR_NOT_FOUND = range(6)
 FF_NO_MF, FF_NO_DC, FF_NO_SA, FF_CONF_EQ3 = 1, 2, 4, 8
-FF_DEV_OK, FF_DEV_OVERFLOW = 0, 1
+FF_DEV_OK, FF_DEV_OVERFLOW, FF_DEV_ERROR = 0, 1, 2
 PAD = 0xFFFFFFFF
 
 
@@ -142,7 +142,8 @@ EXPORTS = {
     "ff_server_now": (ctypes.c_double, [ctypes.c_void_p]),
     "ff_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
                                         ctypes.POINTER(ff_params), ctypes.POINTER(ff_output),
-                                        ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
+                                        ctypes.c_double, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
     "ff_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
                                       ctypes.POINTER(ctypes.c_int32)]),
     "ff_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
@@ -494,7 +495,10 @@ class Server:
         return float(_lib.ff_server_now(self.h))
 
     def submit(self, rig: int, frame: Dict, out: "Output", params: Optional[Params] = None,
-               arrival_s: float = 0.0) -> int:
+               arrival_s: Optional[float] = None, stream=None) -> int:
+        """Queue a frame; it arrives at `arrival_s` on the server clock (None: now).  Work
+        queued on `stream` (default: torch's current stream) before this call is complete
+        before the frame is read."""
         ccams, views = Context._views(frame["cams"], frame["depth"], frame.get("conf"),
                                       frame.get("rgb"))
         fr = ff_frame(len(frame["cams"]), ctypes.cast(ccams, ctypes.POINTER(ff_camera)),
@@ -502,24 +506,32 @@ class Server:
         o = out.c()
         prm = (params or Params()).c
         t = ctypes.c_uint64()
+        a = -1.0 if arrival_s is None else float(arrival_s)
         _check(_lib.ff_server_submit(self.h, int(rig), ctypes.byref(fr), ctypes.byref(prm),
-                                     ctypes.byref(o), float(arrival_s), ctypes.byref(t)),
+                                     ctypes.byref(o), a, _stream_ptr(stream), ctypes.byref(t)),
                "ff_server_submit")
         self._keep[t.value] = (frame, out)       # device buffers stay alive until done
         return t.value
 
     def poll(self, ticket: int) -> bool:
+        """True once the frame is done (then its status is checked and the ticket is
+        forgotten)."""
         d = ctypes.c_int32()
-        _check(_lib.ff_server_poll(self.h, ticket, ctypes.byref(d)), "ff_server_poll")
+        st = _lib.ff_server_poll(self.h, ticket, ctypes.byref(d))
+        if d.value:
+            self._keep.pop(ticket, None)
+        _check(st, "ff_server_poll")
         return bool(d.value)
 
     def wait(self, ticket: int):
-        _check(_lib.ff_server_wait(self.h, ticket), "ff_server_wait")
+        st = _lib.ff_server_wait(self.h, ticket)
         self._keep.pop(ticket, None)
+        _check(st, "ff_server_wait")
 
     def drain(self):
-        _check(_lib.ff_server_drain(self.h), "ff_server_drain")
+        st = _lib.ff_server_drain(self.h)
         self._keep.clear()
+        _check(st, "ff_server_drain")
 
     def stats(self) -> Dict:
         s = ff_stats()

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfuseflow.so")
 
 SOURCES = ["fuseflow.hip"]
-DEPS = ["fuseflow.hip", "phases.hpp", "common.hpp", "server.cpp"]
+DEPS = ["fuseflow.hip", "phases.hpp", "common.hpp", "internal.hpp", "server.cpp"]
 
 # -ffp-contract=off keeps every float op separately rounded (no FMA contraction), which
 # the bit-exact cell keys rely on; packed-fp32 instructions are disabled.

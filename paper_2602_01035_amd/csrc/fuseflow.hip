@@ -19,6 +19,7 @@
 
 #include "fuseflow.h"
 #include "common.hpp"
+#include "internal.hpp"
 #include "phases.hpp"
 
 using namespace ff;
@@ -311,6 +312,30 @@ ff_status validate_params(const ff_params* p) {
     if (p->flags & ~15u) return FF_ERR_INVALID_ARG;
     return FF_OK;
 }
+
+}  // namespace
+
+ff_status ff::check_frame(const ff_frame& fr, const ff_params& prm, const ff_output& o) {
+    if (validate_params(&prm) != FF_OK) return FF_ERR_INVALID_ARG;
+    if (fr.n_cams < 1 || fr.n_cams > kMaxCamsPerFrame || !fr.cams || !fr.views)
+        return FF_ERR_INVALID_ARG;
+    if (!o.xyz || !o.weight || !o.count || !o.status) return FF_ERR_INVALID_ARG;
+    if (o.member_ids && !o.member_offsets) return FF_ERR_INVALID_ARG;
+    const bool conf_eq3 = (prm.flags & FF_CONF_EQ3) != 0;
+    uint64_t P = 0;
+    bool all_rgb = true;
+    for (int32_t k = 0; k < fr.n_cams; ++k) {
+        const ff_camera& cm = fr.cams[k];
+        const ff_view& v = fr.views[k];
+        if (!camera_ok(cm) || !v.depth || (!v.conf && !conf_eq3)) return FF_ERR_INVALID_ARG;
+        P += (uint64_t)cm.width * (uint64_t)cm.height;
+        all_rgb = all_rgb && v.rgb;
+    }
+    if (P >= 0xFFFFFFFFull || (o.rgb && !all_rgb)) return FF_ERR_INVALID_ARG;
+    return FF_OK;
+}
+
+namespace {
 
 void drop_graphs(ff_context* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);

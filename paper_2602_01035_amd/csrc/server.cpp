@@ -8,6 +8,14 @@
 // polls its completion event; the next batch can start on another lane while the previous
 // one still runs.  Latency = completion (observed by the scheduler thread) - arrival.
 //
+// Ordering with the caller: at submit an event is recorded on the caller's stream, and
+// the lane waits for it before the frame's batch runs, so work the caller queued before
+// the submit (filling the images, clearing the outputs) completes first.
+//
+// Errors belong to the frame that caused them: a frame the host checks reject is refused
+// at submit; a batch whose launch fails completes its own frames with that status, after
+// the lane's queued work has finished.  Other frames and later submits are not affected.
+//
 // The plain baseline (config.plain = 1) runs the same trace one frame at a time through
 // ff_fuse and starts a frame only after the previous one completed.
 #include <hip/hip_runtime.h>
@@ -26,6 +34,7 @@
 #include <vector>
 
 #include "fuseflow.h"
+#include "internal.hpp"
 
 namespace {
 
@@ -40,6 +49,7 @@ struct Job {
     std::vector<ff_view> views;
     ff_params params;
     ff_output out;
+    hipEvent_t ready;       // recorded on the caller's stream at submit
 };
 
 struct Lane {
@@ -47,12 +57,33 @@ struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    bool synced = false;          // the lane's work is known complete (no event to query)
+    ff_status launch_status = FF_OK;
     std::vector<Job> batch;
 };
 
 bool same_params(const ff_params& a, const ff_params& b) {
     return std::memcmp(&a, &b, sizeof(ff_params)) == 0;
 }
+
+enum TicketPhase : int { kQueued = 0, kRunning = 1, kDone = 2 };
+
+struct TicketState {
+    int phase;
+    ff_status status;
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
 
 }  // namespace
 
@@ -67,11 +98,12 @@ struct ff_server {
     std::condition_variable cv_done;   // frames completed
     std::condition_variable cv_work;   // new submissions
     std::multimap<double, Job> pending;   // by arrival time (ties keep submission order)
-    std::unordered_map<uint64_t, int> state;   // ticket -> 0 queued, 1 running, 2 done
+    std::unordered_map<uint64_t, TicketState> state;
+    std::vector<hipEvent_t> free_events;
     uint64_t next_ticket = 1;
     uint64_t outstanding = 0;
+    ff_status drain_status = FF_OK;       // first failure since the last drain
     bool stop = false;
-    ff_status error = FF_OK;
     // stats (mutex)
     std::vector<double> lat_ms;
     uint64_t frames = 0, pixels = 0, batches = 0, batch_frames = 0;
@@ -83,7 +115,7 @@ struct ff_server {
     }
     void run();
     bool launch(Lane& L, double t);
-    void complete(Lane& L, double t);
+    void complete(Lane& L, double t, ff_status st);
 };
 
 bool ff_server::launch(Lane& L, double t) {
@@ -98,46 +130,67 @@ bool ff_server::launch(Lane& L, double t) {
         if (px + j.pixels > lane_px || cams + j.cams.size() > (uint64_t)cfg.max_cameras) break;
         px += j.pixels;
         cams += j.cams.size();
-        state[j.ticket] = 1;
+        state[j.ticket].phase = kRunning;
         L.batch.push_back(std::move(j));
         it = pending.erase(it);
     }
     if (L.batch.empty()) return false;
     std::vector<ff_frame> frames(L.batch.size());
     std::vector<ff_output> outs(L.batch.size());
+    ff_status st = FF_OK;
     for (size_t i = 0; i < L.batch.size(); ++i) {
         frames[i].n_cams = (int32_t)L.batch[i].cams.size();
         frames[i].cams = L.batch[i].cams.data();
         frames[i].views = L.batch[i].views.data();
         outs[i] = L.batch[i].out;
+        // the caller's work queued before the submit comes first
+        if (st == FF_OK && hipStreamWaitEvent(L.stream, L.batch[i].ready, 0) != hipSuccess)
+            st = FF_ERR_HIP;
     }
-    ff_status st;
-    if (cfg.plain)
-        st = ff_fuse(L.ctx, frames[0].n_cams, frames[0].cams, frames[0].views,
-                     &L.batch[0].params, &outs[0], L.stream);
-    else
-        st = ff_fuse_batch(L.ctx, (int32_t)frames.size(), frames.data(), &L.batch[0].params,
-                           outs.data(), L.stream);
-    if (st == FF_OK && hipEventRecord(L.done, L.stream) != hipSuccess) st = FF_ERR_HIP;
-    if (st != FF_OK) error = st;
-    L.busy = true;     // completion (or the error) is reported through complete()
+    if (st == FF_OK) {
+        if (cfg.plain)
+            st = ff_fuse(L.ctx, frames[0].n_cams, frames[0].cams, frames[0].views,
+                         &L.batch[0].params, &outs[0], L.stream);
+        else
+            st = ff_fuse_batch(L.ctx, (int32_t)frames.size(), frames.data(),
+                               &L.batch[0].params, outs.data(), L.stream);
+    }
+    // completion is reported once the lane's queued work has finished, also after a
+    // failed launch (part of the batch may have been queued)
+    if (hipEventRecord(L.done, L.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(L.stream);
+        (void)hipGetLastError();
+        L.synced = true;
+        if (st == FF_OK) st = FF_ERR_HIP;
+    }
+    L.launch_status = st;
+    L.busy = true;
     ++batches;
     batch_frames += L.batch.size();
     return true;
 }
 
-void ff_server::complete(Lane& L, double t) {
+void ff_server::complete(Lane& L, double t, ff_status st) {
     for (Job& j : L.batch) {
-        state[j.ticket] = 2;
-        if (first_arrival < 0 || j.arrival < first_arrival) first_arrival = j.arrival;
-        lat_ms.push_back((t - j.arrival) * 1e3);
-        ++frames;
-        pixels += j.pixels;
+        TicketState& ts = state[j.ticket];
+        ts.phase = kDone;
+        ts.status = st;
+        if (st != FF_OK && drain_status == FF_OK) drain_status = st;
+        free_events.push_back(j.ready);
+        if (st == FF_OK) {
+            if (first_arrival < 0 || j.arrival < first_arrival) first_arrival = j.arrival;
+            lat_ms.push_back((t - j.arrival) * 1e3);
+            ++frames;
+            pixels += j.pixels;
+        }
         --outstanding;
     }
-    last_done = std::max(last_done, t);
+    if (st == FF_OK) last_done = std::max(last_done, t);
     L.batch.clear();
     L.busy = false;
+    L.synced = false;
+    L.launch_status = FF_OK;
 }
 
 void ff_server::run() {
@@ -148,13 +201,19 @@ void ff_server::run() {
         // 1. completions (event queries are cheap and non-blocking)
         for (Lane& L : lanes) {
             if (!L.busy) continue;
-            hipError_t q = error == FF_OK ? hipEventQuery(L.done) : hipSuccess;
+            hipError_t q = L.synced ? hipSuccess : hipEventQuery(L.done);
             if (q == hipSuccess) {
-                complete(L, now());
+                complete(L, now(), L.launch_status);
                 progressed = true;
             } else if (q != hipErrorNotReady) {
-                error = FF_ERR_HIP;
-                complete(L, now());
+                // the event cannot be queried: wait for the lane's work itself before its
+                // frames are reported done
+                (void)hipGetLastError();
+                lk.unlock();
+                (void)hipStreamSynchronize(L.stream);
+                (void)hipGetLastError();
+                lk.lock();
+                complete(L, now(), FF_ERR_HIP);
                 progressed = true;
             }
         }
@@ -229,9 +288,7 @@ ff_status ff_server_create(ff_server** out, int device, const ff_server_config* 
     s->cfg = c;
     s->lane_px = lo;
     s->t0 = Clock::now();
-    int prev = 0;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(device);
+    DeviceGuard g(device);
     s->lanes.resize(c.lanes);
     ff_status st = FF_OK;
     for (Lane& L : s->lanes) {
@@ -243,7 +300,6 @@ ff_status ff_server_create(ff_server** out, int device, const ff_server_config* 
             break;
         }
     }
-    (void)hipSetDevice(prev);
     if (st != FF_OK) {
         ff_server_destroy(s);
         return st;
@@ -261,12 +317,15 @@ void ff_server_destroy(ff_server* s) {
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    DeviceGuard g(s->device);
     for (Lane& L : s->lanes) {
         if (L.stream) (void)hipStreamSynchronize(L.stream);
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.stream) (void)hipStreamDestroy(L.stream);
         if (L.ctx) ff_context_destroy(L.ctx);
     }
+    for (auto& kv : s->pending) s->free_events.push_back(kv.second.ready);
+    for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
     delete s;
 }
 
@@ -276,10 +335,11 @@ double ff_server_now(const ff_server* s) { return s ? s->now() : 0.0; }
 
 ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
                            const ff_params* params, const ff_output* out, double arrival_s,
-                           uint64_t* ticket) {
-    if (!s || !frame || !params || !out || !ticket || frame->n_cams < 1 || !frame->cams ||
-        !frame->views)
-        return FF_ERR_INVALID_ARG;
+                           void* stream, uint64_t* ticket) {
+    if (!s || !frame || !params || !out || !ticket) return FF_ERR_INVALID_ARG;
+    // the host checks of the fusion call, for this frame alone
+    ff_status st = ff::check_frame(*frame, *params, *out);
+    if (st != FF_OK) return st;
     Job j;
     j.rig = rig_id;
     j.cams.assign(frame->cams, frame->cams + frame->n_cams);
@@ -287,19 +347,31 @@ ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
     j.params = *params;
     j.out = *out;
     j.pixels = 0;
-    for (const ff_camera& c : j.cams) {
-        if (c.width < 1 || c.height < 1) return FF_ERR_INVALID_ARG;
-        j.pixels += (uint64_t)c.width * (uint64_t)c.height;
-    }
+    for (const ff_camera& c : j.cams) j.pixels += (uint64_t)c.width * (uint64_t)c.height;
     if (j.pixels > s->lane_px || j.cams.size() > (size_t)s->cfg.max_cameras) return FF_ERR_OOM;
+    DeviceGuard g(s->device);
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->error != FF_OK) return s->error;
         if (s->pending.size() >= (size_t)s->cfg.max_pending) return FF_ERR_BUSY;
+        if (s->free_events.empty()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return FF_ERR_HIP;
+            }
+            s->free_events.push_back(e);
+        }
+        j.ready = s->free_events.back();
+        if (hipEventRecord(j.ready, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) {
+            (void)hipGetLastError();
+            return FF_ERR_HIP;
+        }
+        s->free_events.pop_back();
         j.ticket = s->next_ticket++;
-        j.arrival = std::max(arrival_s, 0.0);
+        // an arrival in the past (or none given) is the moment of this call
+        j.arrival = std::max(arrival_s, s->now());
         *ticket = j.ticket;
-        s->state[j.ticket] = 0;
+        s->state[j.ticket] = TicketState{kQueued, FF_OK};
         ++s->outstanding;
         const double a = j.arrival;
         s->pending.emplace(a, std::move(j));
@@ -313,8 +385,11 @@ ff_status ff_server_poll(ff_server* s, uint64_t ticket, int32_t* done) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->state.find(ticket);
     if (it == s->state.end()) return FF_ERR_NOT_FOUND;
-    *done = it->second == 2 ? 1 : 0;
-    return s->error;
+    *done = it->second.phase == kDone ? 1 : 0;
+    if (!*done) return FF_OK;
+    const ff_status st = it->second.status;
+    s->state.erase(it);
+    return st;
 }
 
 ff_status ff_server_wait(ff_server* s, uint64_t ticket) {
@@ -322,15 +397,26 @@ ff_status ff_server_wait(ff_server* s, uint64_t ticket) {
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->state.find(ticket);
     if (it == s->state.end()) return FF_ERR_NOT_FOUND;
-    s->cv_done.wait(lk, [&] { return s->state[ticket] == 2 || s->error != FF_OK; });
-    return s->error;
+    s->cv_done.wait(lk, [&] {
+        auto f = s->state.find(ticket);
+        return f == s->state.end() || f->second.phase == kDone;
+    });
+    it = s->state.find(ticket);
+    if (it == s->state.end()) return FF_ERR_NOT_FOUND;   // reported by a concurrent call
+    const ff_status st = it->second.status;
+    s->state.erase(it);
+    return st;
 }
 
 ff_status ff_server_drain(ff_server* s) {
     if (!s) return FF_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] { return s->outstanding == 0 || s->error != FF_OK; });
-    return s->error;
+    s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+    // every ticket is done: their statuses are reported here, once
+    s->state.clear();
+    const ff_status st = s->drain_status;
+    s->drain_status = FF_OK;
+    return st;
 }
 
 ff_status ff_server_stats(const ff_server* cs, ff_stats* st) {
@@ -360,7 +446,7 @@ ff_status ff_server_stats(const ff_server* cs, ff_stats* st) {
         const double span = s->last_done - s->first_arrival;
         st->px_per_s = span > 0 ? (double)s->pixels / span : 0.0;
     }
-    return s->error;
+    return FF_OK;
 }
 
 ff_status ff_server_reset_stats(ff_server* s) {

@@ -147,7 +147,9 @@ def test_server_admission_by_footprint(ff):
     out = ff.Output(small.pixels)
     t = srv.submit(0, ds, out)
     srv.wait(t)
-    assert srv.poll(t)
+    with pytest.raises(ff.FuseFlowError) as e:      # a waited ticket is forgotten
+        srv.poll(t)
+    assert e.value.status == ff.FF_ERR_NOT_FOUND
     assert out.result()["count"] == len(O.fuse_frame(small)["keys"])
     srv.close()
 
@@ -261,18 +263,78 @@ def test_batch_at_frame_limit(ff):
     ctx.close()
 
 
-def test_server_reports_a_failed_frame(ff):
-    """A frame the library rejects (no confidence without FF_CONF_EQ3: refused on the host
-    before any launch) surfaces as an error from drain and from later submits; it does not
-    hang the scheduler."""
+def test_server_rejects_a_bad_frame_alone(ff):
+    """A frame the host checks reject (no confidence without FF_CONF_EQ3) is refused at its
+    own submit; frames before and after it are accepted and complete normally."""
     print("[case] server error path", flush=True)
     f = cached_frame("c1")
     dev = ff.to_device(f)
     srv = ff.Server(hbm_budget_bytes=1 << 30, lanes=2, max_batch_frames=2)
-    srv.submit(0, dict(cams=dev["cams"], depth=dev["depth"]), ff.Output(f.pixels))
+    outs = [ff.Output(f.pixels) for _ in range(2)]
+    t0 = srv.submit(0, dev, outs[0])
     with pytest.raises(ff.FuseFlowError) as e:
-        srv.drain()
+        srv.submit(1, dict(cams=dev["cams"], depth=dev["depth"]), ff.Output(f.pixels))
     assert e.value.status == ff.FF_ERR_INVALID_ARG
-    with pytest.raises(ff.FuseFlowError):
-        srv.submit(0, dev, ff.Output(f.pixels))
+    t1 = srv.submit(0, dev, outs[1])
+    srv.wait(t0)
+    done = False
+    while not done:
+        done = srv.poll(t1)
+    srv.drain()
+    ref = O.fuse_frame(f)
+    for o in outs:
+        compare(o.result(), ref, check_members=False, label="around a rejected frame")
+    srv.close()
+
+
+def test_server_default_arrival_is_the_submit(ff):
+    """A submit without an arrival time arrives when it is made: its latency is at most the
+    wall time from the submit to its completion, however long the server existed before."""
+    import time
+    print("[case] default arrival", flush=True)
+    f = cached_frame("c1")
+    dev = ff.to_device(f)
+    srv = ff.Server(hbm_budget_bytes=1 << 30, lanes=2, max_batch_frames=2)
+    time.sleep(0.3)
+    out = ff.Output(f.pixels)
+    t = time.perf_counter()
+    tk = srv.submit(0, dev, out)
+    srv.wait(tk)
+    wall_ms = (time.perf_counter() - t) * 1e3
+    st = srv.stats()
+    assert st["frames"] == 1 and 0 < st["max_ms"] <= wall_ms + 0.5, (st, wall_ms)
+    srv.close()
+
+
+def test_server_waits_for_the_callers_stream(ff):
+    """Inputs written by torch on a side stream right before the submit (with that stream
+    passed) are complete when the server reads them: the result equals ff_fuse of the same
+    frame.  The outputs are cleared on that stream too."""
+    import torch
+    print("[case] caller stream ordering", flush=True)
+    f = cached_frame("c2")
+    src = ff.to_device(f)
+    ref = _alone(ff, src)
+    srv = ff.Server(hbm_budget_bytes=2 << 30, lanes=2, max_batch_frames=2)
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        dst = dict(cams=src["cams"], depth=[torch.empty_like(d) for d in src["depth"]],
+                   conf=[torch.empty_like(c) for c in src["conf"]],
+                   rgb=[torch.empty_like(r) for r in src["rgb"]])
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            big = torch.empty(64 << 20, device="cuda")
+            for _ in range(8):            # keep the side stream busy before the copies
+                big.mul_(1.0001)
+            for k in ("depth", "conf", "rgb"):
+                for a, b in zip(dst[k], src[k]):
+                    a.copy_(b)
+            out = ff.Output(f.pixels, rgb=True)
+            out.count.fill_(0)
+        tk = srv.submit(0, dst, out, stream=side)
+        srv.wait(tk)
+        g = out.result()
+        for k in KEYS:
+            assert np.array_equal(g[k], ref[k]), (rep, k)
+        del big
     srv.close()
