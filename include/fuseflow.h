@@ -267,6 +267,17 @@ ff_status ff_emc(ff_context* ctx, int32_t n_cams, const ff_camera* cams, const f
                  const float* xyz, const uint32_t* count, uint32_t capacity,
                  const ff_emc_params* params, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): ff_emc without a context.  Same
+ * arguments and result as ff_emc (the same kernels, bit-identical output), on the calling
+ * thread's current device.  The camera records and the partial sums live in one static
+ * device array of the library (about 64 KiB per device, held until the process ends);
+ * nothing is allocated per call.  At most 64 cameras (FF_ERR_INVALID_ARG beyond).  Calls
+ * that overlap on one device share that array and race: order them on one stream. */
+ff_status ff_emc_noalloc(int32_t n_cams, const ff_camera* cams, const ff_view* views,
+                         const float* xyz, const uint32_t* count, uint32_t capacity,
+                         const ff_emc_params* params, double* out, void* stream);
+
 /* ------------------------------------------------------------------------------ serving
  * A streaming loop over several rigs (the paper's per-frame statelessness, Sec. II.1, is
  * what makes frames of different rigs independent work).  Frames are admitted as they

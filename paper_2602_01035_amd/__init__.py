@@ -132,6 +132,10 @@ EXPORTS = {
                               ctypes.POINTER(ff_view), ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_uint32, ctypes.POINTER(ff_emc_params), ctypes.c_void_p,
                               ctypes.c_void_p]),
+    "ff_emc_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ff_camera),
+                                      ctypes.POINTER(ff_view), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_uint32, ctypes.POINTER(ff_emc_params),
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "ff_probe_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ff_probe_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_probe)]),
     "ff_server_config_default": (None, [ctypes.POINTER(ff_server_config)]),
@@ -567,6 +571,22 @@ def confidence(cams, depth: Sequence, out: Optional[Sequence] = None, alpha: flo
     _check(_lib.ff_confidence(n, ccams, views, ptrs, ctypes.byref(prm), _stream_ptr(stream)),
            "ff_confidence")
     return list(out)
+
+
+def emc_noalloc(cams, depth: Sequence, xyz, count, capacity: int, res, c_occ: float = 0.003,
+                stride: int = 1, stream=None):
+    """Eq. 12 through ff_emc_noalloc (no context, nothing allocated by the library): the
+    fused points `xyz` (device float32 [capacity][3]) with `count` (device uint32/int32 [1])
+    against these depth maps; the result goes to `res` (device float64 [3]: E_MC in metres,
+    points used, mean cameras seeing a used point).  Asynchronous on `stream`."""
+    ccams, views = Context._views(cams, depth, None, None)
+    prm = ff_emc_params()
+    _lib.ff_emc_params_default(ctypes.byref(prm))
+    prm.c_occ, prm.stride = float(c_occ), int(stride)
+    _check(_lib.ff_emc_noalloc(len(cams), ccams, views, xyz.data_ptr(), count.data_ptr(),
+                               int(capacity), ctypes.byref(prm), res.data_ptr(),
+                               _stream_ptr(stream)), "ff_emc_noalloc")
+    return res
 
 
 def to_device(frame, device="cuda", with_rgb=True) -> Dict:

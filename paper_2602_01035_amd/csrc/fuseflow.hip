@@ -127,6 +127,40 @@ __global__ __launch_bounds__(kBlock) void k_emc_final(const double* part, int nb
     }
 }
 
+// Allocation-free E_MC: the camera records and the per-workgroup partial sums live in a
+// file-scope device array instead of a context workspace.  The records arrive as kernel
+// arguments (no host staging buffer), kNoAllocCamsPerLaunch per launch.
+constexpr int kNoAllocMaxCams = 64;
+constexpr int kNoAllocCamsPerLaunch = 16;
+constexpr size_t kNoAllocCamBytes = ((sizeof(DevCam) * kNoAllocMaxCams + 255) / 256) * 256;
+constexpr size_t kNoAllocScratchBytes = kNoAllocCamBytes + (size_t)kEmcBlocks * 3 * sizeof(double);
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+struct EmcCamArgs {
+    float R[9], t[3];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    const float* depth;
+};
+struct EmcCamChunk {
+    EmcCamArgs cam[kNoAllocCamsPerLaunch];
+};
+
+// camera records base .. base + n - 1 of the scratch table, one thread per camera
+__global__ __launch_bounds__(64) void k_emc_cams(EmcCamChunk chunk, DevCam* dst, int base, int n) {
+    const int k = threadIdx.x;
+    if (k >= n) return;
+    const EmcCamArgs& a = chunk.cam[k];
+    DevCam d{};
+    for (int i = 0; i < 9; ++i) d.R[i] = a.R[i];
+    for (int i = 0; i < 3; ++i) d.t[i] = a.t[i];
+    d.fx = a.fx; d.fy = a.fy; d.cx = a.cx; d.cy = a.cy;
+    d.W = a.W; d.H = a.H;
+    d.depth = a.depth;
+    dst[base + k] = d;
+}
+
 // ============================================================================ host side
 
 namespace {
@@ -1097,6 +1131,75 @@ ff_status ff_emc(ff_context* c, int32_t n_cams, const ff_camera* cams, const ff_
     FF_HIP(hipGetLastError());
     FF_HIP(hipEventRecord(c->last, s));
     c->have_last = true;
+    return FF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device address of `scratch` on each device, taken once per device with that device
+// current (in host code the array's name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+ff_status scratch_on_current_device(char** out) {
+    int dev = -1;
+    FF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return FF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        FF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return FF_ERR_HIP;
+        g_scratch[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch[dev];
+    return FF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ff_status ff_emc_noalloc(int32_t n_cams, const ff_camera* cams, const ff_view* views,
+                         const float* xyz, const uint32_t* count, uint32_t capacity,
+                         const ff_emc_params* prm, double* out, void* stream) {
+    if (n_cams < 1 || !cams || !views || !xyz || !count || !prm || !out || prm->stride < 1 ||
+        !std::isfinite(prm->c_occ) || prm->c_occ < 0.0f)
+        return FF_ERR_INVALID_ARG;
+    if (n_cams > kNoAllocMaxCams) return FF_ERR_INVALID_ARG;     // beyond the scratch table
+    for (int32_t k = 0; k < n_cams; ++k)
+        if (cams[k].width < 1 || cams[k].height < 1 || !views[k].depth) return FF_ERR_INVALID_ARG;
+    char* base = nullptr;
+    ff_status st = scratch_on_current_device(&base);
+    if (st != FF_OK) return st;
+    DevCam* dcams = reinterpret_cast<DevCam*>(base);
+    double* part = reinterpret_cast<double*>(base + kNoAllocCamBytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int32_t b = 0; b < n_cams; b += kNoAllocCamsPerLaunch) {
+        EmcCamChunk chunk{};
+        const int n = std::min<int32_t>(kNoAllocCamsPerLaunch, n_cams - b);
+        for (int k = 0; k < n; ++k) {
+            const ff_camera& c = cams[b + k];
+            EmcCamArgs& a = chunk.cam[k];
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) a.R[i * 3 + j] = c.world_to_cam[i * 4 + j];
+                a.t[i] = c.world_to_cam[i * 4 + 3];
+            }
+            a.fx = c.fx; a.fy = c.fy; a.cx = c.cx; a.cy = c.cy;
+            a.W = c.width; a.H = c.height;
+            a.depth = views[b + k].depth;
+        }
+        hipLaunchKernelGGL(k_emc_cams, dim3(1), dim3(64), 0, s, chunk, dcams, (int)b, n);
+    }
+    const uint64_t m = ((uint64_t)capacity + (uint64_t)prm->stride - 1) / (uint64_t)prm->stride;
+    const int nb = (int)std::max<uint64_t>(1, std::min<uint64_t>(kEmcBlocks, (m + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_emc, dim3(nb), dim3(kBlock), 0, s, dcams, n_cams, xyz, count, capacity,
+                       prm->c_occ, (uint32_t)prm->stride, part);
+    hipLaunchKernelGGL(k_emc_final, dim3(1), dim3(kBlock), 0, s, part, nb, out);
+    FF_HIP(hipGetLastError());
     return FF_OK;
 }
 
