@@ -62,6 +62,8 @@ struct CamLite {
     float fx, fy, cx, cy;
     int32_t W, H;
     uint32_t rank, pix_off;
+    uint32_t frame;          // frame index in the batch
+    uint32_t frame_cam;      // index of the camera within its frame (class mask bit)
     float invW;              // 1 / W, for a quick first guess of y = pixel / W
     // field-of-view fast path: cx + 1/2, cy + 1/2, and the largest floats below
     // W - m, H - m (clearly inside) and W + m, H + m (not clearly outside), m = 1/16 px
@@ -101,6 +103,15 @@ struct CallHdr {
     uint32_t sort_items, lds_cams;
     uint32_t any_mids;
     uint32_t key64_ok;               // the key-width bound allows keys wider than 32 bits
+    uint32_t cls_lanes;              // log2 of the camera slots per coarse cell (class phase)
+};
+
+// Field-of-view class of every camera of a frame for one occupied coarse cell: bit j of
+// in_all is set when every point of the cell's box is in view of the frame's camera j by
+// the exact float32 test, bit j of partial when neither that nor "no point is" could be
+// shown (those points take the exact per-point test); cameras in neither mask see none.
+struct CamClass {
+    uint64_t in_all, partial;
 };
 
 // per pixel tile: AABB partial (order-preserving encodings) and gated count
@@ -135,14 +146,16 @@ enum PhaseKind : uint32_t {
     PH_BACKPROJECT = 0, PH_TILE_REDUCE = 1, PH_HIST = 2, PH_SCAN_A = 3, PH_SCAN_M = 4,
     PH_SCAN_B = 5, PH_KEYS = 6, PH_RADIX_UP = 7, PH_RADIX_SCAN = 8, PH_RADIX_DOWN = 9,
     PH_HEAD_COUNT = 10, PH_HEAD_SCAN = 11, PH_HEAD_WRITE = 12, PH_CELLS = 13, PH_FINAL = 14,
-    PH_CAM_PREP = 15, PH_CONF = 16, PH_COUNT = 17
+    PH_CAM_PREP = 15, PH_CONF = 16, PH_CLASS = 17, PH_COUNT = 18
 };
 
 constexpr int kEmcBlocks = 2048;         // workgroups of the E_MC evaluator
 constexpr int kHistTiles = 4;            // pixel tiles per coarse-histogram workgroup
 
-// trace slot of the Eq. 3 confidence phase (the radix passes use 16 .. 30)
+// trace slots of the Eq. 3 confidence phase and of the camera classes (the radix passes
+// use 16 .. 30; slots 7 .. 9 are not used by the radix kinds, which map to 16 ..)
 constexpr int kTraceSlotConf = 31;
+constexpr int kTraceSlotClass = 7;
 
 // weights of Eq. 3
 struct ConfWeights {

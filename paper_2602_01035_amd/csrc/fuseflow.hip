@@ -48,6 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(Ctx C, uint32_t pass) {
         case PH_FINAL: ph_final(C, item, smem); break;
         case PH_CAM_PREP: ph_cam_prep(C, item, smem); break;
         case PH_CONF: ph_conf(C, item, smem); break;
+        case PH_CLASS: ph_class(C, item, smem); break;
         default: break;
     }
 }
@@ -220,6 +221,7 @@ struct ff_context {
     uint64_t* fine_base = nullptr;
     uint64_t counts_cap = 0;
     uint8_t* level = nullptr;
+    CamClass* cls = nullptr;
     uint64_t* scan_tile = nullptr;
     void* keysA = nullptr;
     void* keysB = nullptr;
@@ -388,12 +390,15 @@ ff_status grow_counts(ff_context* c, uint64_t need, hipStream_t stream) {
     drop(c->counts);
     drop(c->fine_base);
     drop(c->level);
+    drop(c->cls);
     drop(c->scan_tile);
-    c->counts = nullptr; c->fine_base = nullptr; c->level = nullptr; c->scan_tile = nullptr;
+    c->counts = nullptr; c->fine_base = nullptr; c->level = nullptr; c->cls = nullptr;
+    c->scan_tile = nullptr;
     ff_status st;
     if ((st = dalloc(c, (void**)&c->counts, need * 4)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->fine_base, need * 8)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->level, need)) != FF_OK) return st;
+    if ((st = dalloc(c, (void**)&c->cls, need * sizeof(CamClass))) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->scan_tile, ((need + kScanTile - 1) / kScanTile + 1) * 8)) != FF_OK)
         return st;
     c->counts_cap = need;
@@ -416,6 +421,7 @@ Ctx make_ctx(ff_context* c) {
     C.counts = c->counts;
     C.fine_base = c->fine_base;
     C.level = c->level;
+    C.cls = c->cls;
     C.scan_tile = c->scan_tile;
     C.keysA = c->keysA;
     C.keysB = c->keysB;
@@ -602,6 +608,14 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
         add(PH_SCAN_A, H->n_scan_tiles, 0);
         add(PH_SCAN_M, 1, 0);
         add(PH_SCAN_B, H->n_scan_tiles, 0);
+        if (!(prm->flags & FF_NO_DC)) {
+            // camera slots per coarse cell: a power of two >= the largest frame's cameras
+            uint32_t lanes = 0, most = 1;
+            for (int32_t f = 0; f < n_frames; ++f) most = std::max<uint32_t>(most, (uint32_t)frames[f].n_cams);
+            while ((1u << lanes) < most) ++lanes;
+            H->cls_lanes = lanes;
+            add(PH_CLASS, (uint32_t)(((ncounts << lanes) + kBlock - 1) / kBlock), 0);
+        }
     }
     add(PH_KEYS, ntile, 0);
     if (!no_sa) {
@@ -631,6 +645,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
 
 int trace_slot(const Launch& L) {
     if (L.kind == PH_CONF) return kTraceSlotConf;
+    if (L.kind == PH_CLASS) return kTraceSlotClass;
     if (L.kind == PH_RADIX_UP || L.kind == PH_RADIX_SCAN || L.kind == PH_RADIX_DOWN)
         return std::min(30, 16 + 3 * (int)L.pass + (int)(L.kind - PH_RADIX_UP));
     return (int)L.kind;
@@ -751,6 +766,7 @@ void launch_one(const Ctx& C, const Launch& L, uint32_t ncams, const Plan& plan,
         case PH_FINAL: FF_L(PH_FINAL); break;
         case PH_CAM_PREP: FF_L(PH_CAM_PREP); break;
         case PH_CONF: FF_L(PH_CONF); break;
+        case PH_CLASS: FF_L(PH_CLASS); break;
         default: break;
     }
 #undef FF_L
@@ -891,7 +907,8 @@ void ff_params_default(ff_params* p) {
 uint64_t ff_workspace_bytes(uint64_t max_pixels, int32_t max_cameras, int32_t max_frames) {
     const Sizes s = sizes_for(max_pixels, max_cameras, max_frames);
     return s.desc + sizeof(BatchState) + sizeof(FrameState) * (uint64_t)max_frames +
-           s.px_tiles * (sizeof(TilePart) + 4) + s.counts * 13 + s.scan * 8 + 2 * s.keys * 12 +
+           s.px_tiles * (sizeof(TilePart) + 4) + s.counts * (13 + sizeof(CamClass)) +
+           s.scan * 8 + 2 * s.keys * 12 +
            s.dhist * 4 + kMaxDigits * 4 + s.sort_tiles * 4 + s.cell * 4 + s.keys * 4 +
            sizeof(CamLite) * (uint64_t)max_cameras + (max_pixels + max_cameras + 64) * 4 +
            (max_pixels + 4) * 4 + (uint64_t)kEmcBlocks * 24 + 4096;
@@ -953,6 +970,7 @@ ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
     if ((st = dalloc(c, (void**)&c->counts, s.counts * 4)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->fine_base, s.counts * 8)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->level, s.counts)) != FF_OK) return fail(st);
+    if ((st = dalloc(c, (void**)&c->cls, s.counts * sizeof(CamClass))) != FF_OK) return fail(st);
     c->counts_cap = s.counts;
     if ((st = dalloc(c, (void**)&c->scan_tile, s.scan * 8)) != FF_OK) return fail(st);
     if ((st = dalloc(c, &c->keysA, s.keys * 8)) != FF_OK) return fail(st);
@@ -1244,7 +1262,7 @@ ff_status ff_probe_read(ff_context* c, ff_probe* out) {
 const char* ff_trace_slot_name(int32_t slot) {
     static const char* names[] = {"backproject_aabb", "tile_reduce", "coarse_hist",
                                   "coarse_scan_a", "coarse_scan_m", "coarse_scan_b", "keys",
-                                  "radix_up", "radix_scan", "radix_down", "head_count",
+                                  "camera_classes", "radix_scan", "radix_down", "head_count",
                                   "head_scan", "head_write", "cells_top3_consistency_fuse",
                                   "final", "cam_prep"};
     if (slot >= 0 && slot < 16) return names[slot];

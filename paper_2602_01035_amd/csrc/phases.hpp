@@ -32,6 +32,7 @@ struct Ctx {
     uint32_t* counts;        // [F][G^3] gated points per coarse cell
     uint64_t* fine_base;     // [F][G^3] first dense fine index of each coarse cell
     uint8_t* level;          // [F][G^3] refinement level of each coarse cell
+    CamClass* cls;           // [F][G^3] field-of-view class of the frame's cameras (occupied cells)
     uint64_t* scan_tile;     // [n_scan_tiles] tile sums, then exclusive prefixes
     void* keysA;             // sort keys (u32 or u64 by BatchState::key64)
     void* keysB;
@@ -559,6 +560,8 @@ __device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem
         for (int a = 0; a < 3; ++a) { cl.t[a] = me.t[a]; cl.c[a] = me.c[a]; }
         cl.fx = me.fx; cl.fy = me.fy; cl.cx = me.cx; cl.cy = me.cy;
         cl.W = me.W; cl.H = me.H; cl.rank = rank; cl.pix_off = me.pix_off;
+        cl.frame = me.frame;
+        cl.frame_cam = i - fr.cam_begin;
         cl.invW = 1.0f / (float)me.W;
         cl.cxh = me.cx + 0.5f;
         cl.cyh = me.cy + 0.5f;
@@ -838,6 +841,75 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem)
     flush(frame);
 }
 
+// ---------------------------------------------------------------- field-of-view classes
+// For an occupied coarse cell and each camera of its frame: is every point of the cell in
+// view by the exact float32 test of Eq. 4 (in front, nearest pixel floor(u + 1/2) inside
+// the image), is none, or neither?  The points of coarse cell ci satisfy
+// floor((p - bmin) 2^-e) = ci with one rounding in the subtraction, so they lie in the box
+// bmin + [ci, ci + 1] s0 widened by that rounding.  Over a box entirely in front of the
+// camera, the projection is a projective map, which takes the box's convex hull to the
+// convex hull of its corners' images: u and v over the box lie between their values at
+// the eight corners.  Those are computed in double, and a decision is taken only with a
+// margin far above the float32 error of the per-point computation (a few units in the
+// last place of the terms of X, Y, Z, the quotient and the sums), so a class never
+// disagrees with the exact per-point test; everything else is "partial" and takes that
+// test.
+__device__ __forceinline__ void classify_box(const DevCam& cm, const double lo[3],
+                                             const double hi[3], bool& in_all, bool& partial) {
+    in_all = false;
+    partial = false;
+    double zmin = INFINITY, zmax = -INFINITY, umin = INFINITY, umax = -INFINITY;
+    double vmin = INFINITY, vmax = -INFINITY, mx = 0.0, mz = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double q0 = (k & 1) ? hi[0] : lo[0];
+        const double q1 = (k & 2) ? hi[1] : lo[1];
+        const double q2 = (k & 4) ? hi[2] : lo[2];
+        const double r0 = (double)cm.R[0] * q0, r1 = (double)cm.R[1] * q1, r2 = (double)cm.R[2] * q2;
+        const double r3 = (double)cm.R[3] * q0, r4 = (double)cm.R[4] * q1, r5 = (double)cm.R[5] * q2;
+        const double r6 = (double)cm.R[6] * q0, r7 = (double)cm.R[7] * q1, r8 = (double)cm.R[8] * q2;
+        const double X = ((r0 + r1) + r2) + (double)cm.t[0];
+        const double Y = ((r3 + r4) + r5) + (double)cm.t[1];
+        const double Z = ((r6 + r7) + r8) + (double)cm.t[2];
+        // magnitudes of the terms of X, Y, Z (their float32 rounding is relative to these)
+        const double ax = fabs(r0) + fabs(r1) + fabs(r2) + fabs((double)cm.t[0]);
+        const double ay = fabs(r3) + fabs(r4) + fabs(r5) + fabs((double)cm.t[1]);
+        const double az = fabs(r6) + fabs(r7) + fabs(r8) + fabs((double)cm.t[2]);
+        mx = fmax(mx, fmax(ax, ay));
+        mz = fmax(mz, az);
+        zmin = fmin(zmin, Z);
+        zmax = fmax(zmax, Z);
+        if (Z > 0.0) {
+            const double rz = 1.0 / Z;
+            const double u = (double)cm.fx * (X * rz) + (double)cm.cx;
+            const double v = (double)cm.fy * (Y * rz) + (double)cm.cy;
+            umin = fmin(umin, u); umax = fmax(umax, u);
+            vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+        }
+    }
+    // Far from the float32 range limits the per-point error is relative to the terms;
+    // near them (overflow of a term, subnormal terms) no class is claimed.
+    if (!(mx <= 1e36 && mz <= 1e36)) { partial = true; return; }
+    const double ez = 1e-5 * mz + 1e-30;               // >> float32 error of Z
+    if (zmax < -ez) return;                            // wholly behind: sees none
+    if (!(zmin > ez)) { partial = true; return; }      // straddles Z = 0
+    // The float32 u of a point differs from the real one by at most about
+    // 4e-7 (|f| mx + |u - c| mz) / Z (errors of X and Z carried through X / Z and the
+    // scaling by f) plus a few roundings of |u|: margins 25 times that, plus 1/16 px.
+    const double eu = fmax(fabs(umin - (double)cm.cx), fabs(umax - (double)cm.cx));
+    const double ev = fmax(fabs(vmin - (double)cm.cy), fabs(vmax - (double)cm.cy));
+    const double du = 1e-5 * ((fabs((double)cm.fx) * mx + eu * mz) / zmin + fabs(umin) +
+                              fabs(umax) + fabs((double)cm.cx)) + 0.0625;
+    const double dv = 1e-5 * ((fabs((double)cm.fy) * mx + ev * mz) / zmin + fabs(vmin) +
+                              fabs(vmax) + fabs((double)cm.cy)) + 0.0625;
+    const double W = (double)cm.W, H = (double)cm.H;
+    const bool in = umin >= -0.5 + du && umax <= W - 0.5 - du && vmin >= -0.5 + dv &&
+                    vmax <= H - 0.5 - dv;
+    const bool out = umax < -0.5 - du || umin > W - 0.5 + du || vmax < -0.5 - dv ||
+                     vmin > H - 0.5 + dv;
+    in_all = in;
+    partial = !in && !out;
+}
+
 // ---------------------------------------------------------------- phase: coarse scan
 // span(c) = 8^L(c) dense fine indices for every occupied coarse cell; the exclusive scan
 // over (frame, cell) gives each cell's first dense index.  Three steps: tile sums, a
@@ -936,6 +1008,56 @@ __device__ __forceinline__ void ph_scan_b(const Ctx& C, uint32_t tile, char* sme
             if (idx % per_frame == 0) C.fs[idx / per_frame].fine_begin = run;
         }
         run += sp[i];
+    }
+}
+
+// One thread per (coarse cell, camera slot): the field-of-view class of each camera of the
+// frame for every occupied coarse cell (the per-cell phase reads the class of each
+// representative's coarse cell).  The camera slots of a cell are consecutive lanes of one
+// wave (2^cls_lanes of them, at least the frame's camera count), so two ballots assemble
+// the cell's masks.
+__device__ __forceinline__ void ph_class(const Ctx& C, uint32_t item, char*) {
+    const CallHdr& H = *C.hdr;
+    const DevParams& P = H.prm;
+    if (P.flags & 6u) return;                 // no V (NO_DC) or no grid (NO_SA)
+    const uint32_t lanes = H.cls_lanes;
+    const uint64_t t = (uint64_t)item * kBlock + threadIdx.x;
+    const uint64_t idx = t >> lanes;
+    const uint32_t jj = (uint32_t)(t & ((1u << lanes) - 1u));
+    const uint64_t per_frame = (uint64_t)(P.G * P.G * P.G);
+    bool occ = idx < (uint64_t)H.n_counts && C.counts[idx] != 0u;
+    bool in = false, part = false;
+    if (occ) {
+        const uint32_t f = (uint32_t)(idx / per_frame);
+        const uint32_t lin = (uint32_t)(idx - (uint64_t)f * per_frame);
+        const DevFrame& fr = C.frames[f];
+        if (jj < fr.n_cams) {
+            const FrameState& st = C.fs[f];
+            const uint32_t G = (uint32_t)P.G;
+            const uint32_t ci[3] = {lin % G, (lin / G) % G, lin / (G * G)};
+            const double s0 = 1.0 / (double)st.scale;          // 2^e, exact
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                const double b = (double)st.bmin[a], bx = (double)o2f(st.bmax_o[a]);
+                // widened by the rounding of p - bmin (at most 2^-24 of |p - bmin|)
+                const double eps = 0x1p-22 * (fabs(bx - b) + (double)G * s0) + 0x1p-22 * fabs(b);
+                lo[a] = b + (double)ci[a] * s0 - eps;
+                hi[a] = b + (double)(ci[a] + 1) * s0 + eps;
+                // the last cell also holds every point beyond the grid (a clamped exponent
+                // leaves the extent wider than G s0): up to the frame's maximum
+                if (ci[a] == G - 1) hi[a] = fmax(hi[a], bx + eps);
+            }
+            classify_box(C.cams[fr.cam_begin + jj], lo, hi, in, part);
+        }
+    }
+    const uint64_t bin = __ballot(in), bpart = __ballot(part);
+    const uint32_t l = lane_id(), base = l & ~((1u << lanes) - 1u);
+    if (occ && jj == 0) {
+        const uint64_t m = lanes >= 6 ? ~0ull : ((1ull << (1u << lanes)) - 1ull);
+        CamClass cc;
+        cc.in_all = (bin >> base) & m;
+        cc.partial = (bpart >> base) & m;
+        C.cls[idx] = cc;
     }
 }
 
@@ -1351,8 +1473,8 @@ __device__ __forceinline__ void ph_head_write(const Ctx& C, uint32_t tile, char*
 
 // ---------------------------------------------------------------- cell helpers
 
-// A member of a cell, ranked by confidence first; its pixel id and position are fetched
-// only when needed (a tie in confidence, or once it is a representative).
+// A member of a cell for the full-order ranking; its pixel id and position are fetched
+// only when needed.
 struct Cand {
     float C;
     uint32_t k;      // sorted position
@@ -1466,24 +1588,36 @@ __device__ __forceinline__ void insert_sorted(uint64_t (&s)[N], uint64_t c) {
     s[0] = b[0] ? c : s[0];
 }
 
-// -ln V of representative (cam ri, point p): Eq. 4-7 over the first K-1 views by distance.
-// KV >= K - 1 is the compile-time size of the kept list.  Every camera of the frame is
-// tested; a visible one becomes the 64-bit key (bits of the squared distance, camera rank,
-// camera index).  The bits of a non-negative float order like its value and ranks are
-// unique within a frame, so keys order candidates by (distance, rank).  A branch-free
-// insertion keeps the KV smallest keys sorted (an empty slot holds the largest key).
+// -ln V of representative (camera ri, point p): Eq. 4-7 over the first K-1 views by
+// distance.  KV >= K - 1 is the compile-time size of the kept list.  The field-of-view
+// classes of the point's coarse cell (in_all, partial: bits over the frame's cameras) say
+// which cameras see the whole cell, which see none of it and which need the exact test of
+// this point; only the last take it.  A visible camera becomes the 64-bit key (bits of the
+// squared distance, camera rank, camera index): the bits of a non-negative float order
+// like its value and ranks are unique within a frame, so keys order candidates by
+// (distance, rank).  A branch-free insertion keeps the KV smallest keys sorted.  A camera
+// no lane of the wave can see is skipped as a whole.
 template <int KV>
-__device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const Pt& p,
-                                            uint32_t fcam0, uint32_t fcams, const DevParams& P) {
+__device__ __forceinline__ double neg_log_v(const CamLite* cams, uint32_t own_bit, const Pt& p,
+                                            uint32_t fcam0, uint32_t fcams, uint64_t in_all,
+                                            uint64_t partial, const DevParams& P) {
     const int keep = (P.K < (int)fcams ? P.K : (int)fcams) - 1;
     if (keep <= 0) return 0.0;
     constexpr uint64_t kNone = ~0ull;
     uint64_t best[KV];
 #pragma unroll
     for (int q = 0; q < KV; ++q) best[q] = kNone;
-    for (uint32_t j = fcam0; j < fcam0 + fcams; ++j) {
+    const uint64_t cand = (in_all | partial) & ~(1ull << own_bit);
+    for (uint32_t jj = 0; jj < fcams; ++jj) {
+        const bool c_j = (cand >> jj) & 1ull;
+        if (__ballot(c_j) == 0ull) continue;          // no lane can see this camera
+        const uint32_t j = fcam0 + jj;
         const CamLite& cj = cams[j];
-        const bool vis = in_view_fast(cj, p) & ((int)j != ri);
+        bool vis = c_j && ((in_all >> jj) & 1ull);
+        const bool part = c_j && ((partial >> jj) & 1ull);
+        if (__ballot(part) != 0ull) {
+            if (part) vis = in_view_fast(cj, p);
+        }
         const float dx = p.x - cj.c[0], dy = p.y - cj.c[1], dz = p.z - cj.c[2];
         const float d2 = (dx * dx + dy * dy) + dz * dz;
         const uint64_t c = vis ? ((uint64_t)__float_as_uint(d2) << 32 | (uint64_t)cj.rank << 16 | j)
@@ -1526,6 +1660,7 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, int ri, const P
         // operations): two divisions are cheaper here than two more divergent gathers
         const Pt Q = backproject_ray(cj, ((float)bx[q] - cj.cx) / cj.fx,
                                      ((float)by[q] - cj.cy) / cj.fy, d);
+        // the differences of two floats and their squares are exact in double
         const double ex = (double)p.x - (double)Q.x;
         const double ey = (double)p.y - (double)Q.y;
         const double ez = (double)p.z - (double)Q.z;
@@ -1548,12 +1683,6 @@ template <int CTRL>
 __device__ __forceinline__ float qmovf(float v) {
     return __uint_as_float(qmov<CTRL>(__float_as_uint(v)));
 }
-template <int CTRL>
-__device__ __forceinline__ double qmovd(double v) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint64_t lo = qmov<CTRL>((uint32_t)u), hi = qmov<CTRL>((uint32_t)(u >> 32));
-    return __longlong_as_double((long long)(lo | (hi << 32)));
-}
 constexpr int kQuadXor1 = 0xB1;                 // lanes [1, 0, 3, 2]
 constexpr int kQuadXor2 = 0x4E;                 // lanes [2, 3, 0, 1]
 template <int R> struct QuadBcast { static constexpr int ctrl = R * 0x55; };   // [R, R, R, R]
@@ -1571,102 +1700,92 @@ __device__ __forceinline__ void top3_insert(const CellCtx& X, Cand* rep, int& n,
     if (n < 3) ++n;
 }
 
-// The best three members by confidence alone, as 64-bit keys: the complemented
-// order-preserving bits of C (-0 taken as +0), so that a larger confidence is a smaller
-// key, then the sorted position k.  A branch-free insertion keeps the three smallest keys
-// in order (an empty slot holds the largest key, which no confidence produces).  `tie` is
-// set whenever a confidence equal to a kept one is met: only then can the position/pixel
-// tie-break of the full order change the result, and the caller ranks that cell again in
-// full.
-constexpr uint64_t kNoKey = ~0ull;
-struct Top3 {
-    uint64_t key[3];
+// Confidence as an order-preserving unsigned value (-0 taken as +0): a larger confidence
+// gives a larger value, and none gives 0 (that would be a negative NaN, which fails the
+// gate).
+__device__ __forceinline__ uint32_t conf_bits(float c) { return f2o(c + 0.0f); }
+
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+    return max(min(a, b), min(max(a, b), c));
+}
+
+// The three largest confidence values t0 >= t1 >= t2 of a set (0 = empty slot), kept by
+// a three-instruction insertion network.  `tie` is set whenever a value equal to a kept
+// one is met: only then can the position / pixel tie-break of the full order change the
+// choice or the order of the three, and the caller ranks that cell again in full.  Without
+// a tie each of the three values belongs to exactly one member.
+struct Top3v {
+    uint32_t t0, t1, t2;
     bool tie;
 };
-
-__device__ __forceinline__ uint64_t conf_key(float c, uint32_t k) {
-    return (uint64_t)(~f2o(c + 0.0f)) << 32 | k;
+__device__ __forceinline__ void top3v_push(Top3v& t, uint32_t v) {
+    t.tie |= (v != 0u) & ((v == t.t0) | (v == t.t1) | (v == t.t2));
+    const uint32_t n0 = max(t.t0, v), n1 = med3u(t.t0, t.t1, v), n2 = med3u(t.t1, t.t2, v);
+    t.t0 = n0;
+    t.t1 = n1;
+    t.t2 = n2;
 }
-__device__ __forceinline__ float key_conf(uint64_t key) { return o2f(~(uint32_t)(key >> 32)); }
-
-__device__ __forceinline__ void top3c_insert(Top3& t, uint64_t c) {
-    // equal confidence bits with a kept key: the high words differ by zero
-    const uint32_t d0 = (uint32_t)((c ^ t.key[0]) >> 32), d1 = (uint32_t)((c ^ t.key[1]) >> 32),
-                   d2 = (uint32_t)((c ^ t.key[2]) >> 32);
-    t.tie |= (min(min(d0, d1), d2) == 0u) & (c != kNoKey);
-    insert_sorted(t.key, c);
-}
-
-// merge the partner lane's list (disjoint members) into this lane's
+// merge the partner lane's three (disjoint members) into this lane's
 template <int CTRL>
-__device__ __forceinline__ void top3c_merge(Top3& t) {
-    uint64_t pk[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-        pk[q] = (uint64_t)qmov<CTRL>((uint32_t)(t.key[q] >> 32)) << 32 |
-                qmov<CTRL>((uint32_t)t.key[q]);
+__device__ __forceinline__ void top3v_merge(Top3v& t) {
+    const uint32_t a = qmov<CTRL>(t.t0), b = qmov<CTRL>(t.t1), c = qmov<CTRL>(t.t2);
     t.tie |= qmov<CTRL>(t.tie ? 1u : 0u) != 0u;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) top3c_insert(t, pk[q]);
+    top3v_push(t, a);
+    top3v_push(t, b);
+    top3v_push(t, c);
+}
+template <int CTRL>
+__device__ __forceinline__ uint32_t qmin(uint32_t v) {
+    return min(v, qmov<CTRL>(v));
 }
 
-// Output of one cell from its representatives' values (lane 0 of the quad): joint weights
-// w = C V (Eq. 10) and the normalised weighted mean (Eq. 11); when every weight underflows
-// the same mean is taken in the log domain (softmax of ln C - ln V^-1).
+// Output of one cell from its representatives' values: joint weights w = C V (Eq. 10) and
+// the normalised weighted mean (Eq. 11), taken as a softmax of a = ln C - ln V^-1 so that
+// no weight underflows; the output weight is the mean of the w.  The exponents are formed
+// in double and their exponentials (all <= 1) taken in float32.
 __device__ __forceinline__ void emit_cell(const DevFrame& fr, uint32_t o, int nrep,
                                           const float* Cr, const Pt* pr, const double* expo,
-                                          const double* wv, const uint32_t* rgb3,
-                                          const uint32_t* idr, uint32_t nmem) {
-    double wsum = 0.0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) wsum += r < nrep ? wv[r] : 0.0;
-    double pis[3] = {0.0, 0.0, 0.0};
-    if (wsum > 1e-280) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) pis[r] = (r < nrep ? wv[r] : 0.0) / wsum;
-    } else {
-        double a[3] = {0.0, 0.0, 0.0}, amax = -INFINITY, se = 0.0;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            if (r >= nrep) continue;
-            a[r] = log((double)Cr[r]) - expo[r];
-            amax = a[r] > amax ? a[r] : amax;
-        }
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            pis[r] = r < nrep ? exp(a[r] - amax) : 0.0;
-            se += pis[r];
-        }
-#pragma unroll
-        for (int r = 0; r < 3; ++r) pis[r] /= se;
-    }
-    double x = 0.0, y = 0.0, z = 0.0;
-    double cr = 0.0, cg = 0.0, cb = 0.0;
-    const bool rgb = fr.rgb != nullptr && fr.has_rgb;
+                                          const uint32_t* rgb3, const uint32_t* idr,
+                                          uint32_t nmem) {
+    constexpr double kLog2e = 1.4426950408889634;
+    double a[3], amax = -INFINITY;
+    bool nan = false;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        const double pi = pis[r];
-        if (r < nrep) {
-            x += pi * (double)pr[r].x;
-            y += pi * (double)pr[r].y;
-            z += pi * (double)pr[r].z;
-            cr += pi * (double)(rgb3[r] & 0xFFu);
-            cg += pi * (double)(rgb3[r] >> 8 & 0xFFu);
-            cb += pi * (double)(rgb3[r] >> 16 & 0xFFu);
-        } else {
-            x += pi * 0.0; y += pi * 0.0; z += pi * 0.0;
-        }
+        a[r] = r < nrep ? (double)logf(Cr[r]) - expo[r] : -INFINITY;
+        nan |= a[r] != a[r];
+        amax = a[r] > amax ? a[r] : amax;
     }
-    glob(fr.xyz)[(uint64_t)o * 3 + 0] = (float)x;
-    glob(fr.xyz)[(uint64_t)o * 3 + 1] = (float)y;
-    glob(fr.xyz)[(uint64_t)o * 3 + 2] = (float)z;
-    glob(fr.weight)[o] = (float)(wsum / (double)nrep);
-    if (rgb) {
-        const double v[3] = {cr, cg, cb};
+    if (nan) amax = __longlong_as_double(0x7FF8000000000000ll);   // as the mean of NaNs
+    float e[3], se = 0.0f, wsum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        e[r] = r < nrep ? exp2f((float)((a[r] - amax) * kLog2e)) : 0.0f;
+        se += e[r];
+        wsum += r < nrep ? Cr[r] * exp2f((float)(-expo[r] * kLog2e)) : 0.0f;
+    }
+    float x = 0.0f, y = 0.0f, z = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        if (r >= nrep) continue;
+        const float pi = e[r] / se;
+        x += pi * pr[r].x;
+        y += pi * pr[r].y;
+        z += pi * pr[r].z;
+        cr += pi * (float)(rgb3[r] & 0xFFu);
+        cg += pi * (float)(rgb3[r] >> 8 & 0xFFu);
+        cb += pi * (float)(rgb3[r] >> 16 & 0xFFu);
+    }
+    glob(fr.xyz)[(uint64_t)o * 3 + 0] = x;
+    glob(fr.xyz)[(uint64_t)o * 3 + 1] = y;
+    glob(fr.xyz)[(uint64_t)o * 3 + 2] = z;
+    glob(fr.weight)[o] = wsum / (float)nrep;
+    if (fr.rgb != nullptr && fr.has_rgb) {
+        const float v[3] = {cr, cg, cb};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double t = rint(v[k]);
-            t = t < 0.0 ? 0.0 : (t > 255.0 ? 255.0 : t);
+            float t = rintf(v[k]);
+            t = t > 0.0f ? (t > 255.0f ? 255.0f : t) : 0.0f;     // NaN -> 0
             glob(fr.rgb)[(uint64_t)o * 3 + k] = (uint8_t)t;
         }
     }
@@ -1689,8 +1808,9 @@ __device__ __forceinline__ void wave_sync() {
 // Top-3 representatives (Sec. II.5(2)a), local views and consistency (II.5(2)b, Eq. 4-7),
 // joint weight and fusion (Eq. 10-11), output.  A wave takes 64 cells at a time through
 // three stages that each keep all 64 lanes busy, handing over through its own LDS stage:
-//   A  four lanes per cell rank the members (each lane every fourth member, lists merged
-//      across the quad), 16 cells at a time;
+//   A  cells of at most three members: one lane per cell orders their confidences; larger
+//      cells (and ties): four lanes per cell, each ranking every fourth member, the lists
+//      merged across the quad, 16 cells at a time;
 //   B  the representatives, compacted, one per lane: back-projection, local views, -ln V;
 //   C  one lane per cell: key, joint weights, fused point, outputs.
 // Waves walk groups of 64 cells; the workgroups of one XCD (dispatched round-robin over
@@ -1748,9 +1868,9 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
     for (uint32_t g0 = r0 + (li * wpb + wave) * kStageCells; g0 < r1;
          g0 += n_local * wpb * kStageCells) {
         // member ranges of all 64 cells at once (lane = cell).  A cell of at most three
-        // members needs no selection: its lane loads their confidences and orders them; a
-        // tie among them goes to the quads, which settle it in the full order.  The other
-        // cells are listed for the quads.
+        // members needs no selection: its lane orders their confidences; a tie among them
+        // goes to the quads, which settle it in the full order.  The other cells are listed
+        // for the quads.
         bool big = false;
         {
             const uint32_t s = g0 + lane;
@@ -1762,32 +1882,28 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             bool small = false;
             if (s < r1 && have_cs && a < b && b <= M_tot && b - a <= 3u) {
                 const uint32_t n = b - a;
-                uint64_t kk[3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-                    kk[r] = (uint32_t)r < n
-                                ? conf_key(__uint_as_float(glob(C.conf_sorted)[a + r]), a + r)
-                                : kNoKey;
-                // three-element sorting network, ascending key = descending confidence
-                auto cswap = [](uint64_t& x, uint64_t& y) {
-                    const uint64_t lo = x < y ? x : y, hi = x < y ? y : x;
-                    x = lo;
-                    y = hi;
+                uint32_t v0 = conf_bits(__uint_as_float(glob(C.conf_sorted)[a]));
+                uint32_t v1 = n > 1 ? conf_bits(__uint_as_float(glob(C.conf_sorted)[a + 1])) : 0u;
+                uint32_t v2 = n > 2 ? conf_bits(__uint_as_float(glob(C.conf_sorted)[a + 2])) : 0u;
+                uint32_t k0 = a, k1 = a + 1, k2 = a + 2;
+                // three-element sorting network, descending value; positions ride along
+                auto cswap = [](uint32_t& va, uint32_t& ka, uint32_t& vb, uint32_t& kb) {
+                    const bool sw = vb > va;
+                    const uint32_t tv = sw ? vb : va, tk = sw ? kb : ka;
+                    vb = sw ? va : vb;
+                    kb = sw ? ka : kb;
+                    va = tv;
+                    ka = tk;
                 };
-                cswap(kk[0], kk[1]);
-                cswap(kk[1], kk[2]);
-                cswap(kk[0], kk[1]);
-                const uint32_t h0 = (uint32_t)(kk[0] >> 32), h1 = (uint32_t)(kk[1] >> 32),
-                               h2 = (uint32_t)(kk[2] >> 32);
-                small = !((n > 1 && h0 == h1) || (n > 2 && h1 == h2));
+                cswap(v0, k0, v1, k1);
+                cswap(v1, k1, v2, k2);
+                cswap(v0, k0, v1, k1);
+                small = !((n > 1 && v0 == v1) || (n > 2 && v1 == v2));
                 if (small) {
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        if ((uint32_t)r < n) {
-                            st.sid[lane * 3 + r] = (uint32_t)kk[r];
-                            st.sC[lane * 3 + r] = key_conf(kk[r]);
-                        }
-                    }
+                    st.sid[lane * 3 + 0] = k0;
+                    st.sC[lane * 3 + 0] = o2f(v0);
+                    if (n > 1) { st.sid[lane * 3 + 1] = k1; st.sC[lane * 3 + 1] = o2f(v1); }
+                    if (n > 2) { st.sid[lane * 3 + 2] = k2; st.sC[lane * 3 + 2] = o2f(v2); }
                     if (fr_mids_any) {
                         const int f = last_le(sh.fpix, (int)nf, glob(vals)[a]);
                         const DevFrame& fr = s_frames[f];
@@ -1832,42 +1948,56 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             if (ok) {
                 // this lane's members start + q, start + q + 4, ...: confidences of 4 of
                 // them are loaded together (most cells give a lane one or two members),
-                // then ranked by confidence
-                Top3 t;
-                t.key[0] = t.key[1] = t.key[2] = kNoKey;
-                t.tie = no_mf;                        // all confidences 1: full order
+                // then ranked by value; a second pass over the same members finds which
+                // of them hold the three values (unique unless a tie was seen)
+                auto conf_at = [&](uint32_t k) -> float {
+                    if (have_cs) return __uint_as_float(glob(C.conf_sorted)[k]);
+                    const uint32_t id = glob(vals)[k];
+                    const CamLite& cm = cams[last_le(s_cam_pix, (int)nc, id)];
+                    return glob(cm.conf)[id - cm.pix_off];
+                };
+                Top3v t{0u, 0u, 0u, no_mf};           // all confidences 1: full order
                 if (!no_mf) {
                     for (uint32_t k0 = start + q; k0 < end; k0 += 16u) {
                         float cv[4];
 #pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) {
-                            const uint32_t k = k0 + 4u * jj;
-                            cv[jj] = 0.0f;
-                            if (k < end) {
-                                if (have_cs) {
-                                    cv[jj] = __uint_as_float(glob(C.conf_sorted)[k]);
-                                } else {
-                                    const uint32_t id = glob(vals)[k];
-                                    const CamLite& cm = cams[last_le(s_cam_pix, (int)nc, id)];
-                                    cv[jj] = glob(cm.conf)[id - cm.pix_off];
-                                }
-                            }
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t k = k0 + 4u * u;
+                            cv[u] = k < end ? conf_at(k) : 0.0f;
                         }
 #pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) {
-                            const uint32_t k = k0 + 4u * jj;
-                            top3c_insert(t, k < end ? conf_key(cv[jj], k) : kNoKey);
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t k = k0 + 4u * u;
+                            if (k < end) top3v_push(t, conf_bits(cv[u]));
                         }
                     }
                 }
-                top3c_merge<kQuadXor1>(t);
-                top3c_merge<kQuadXor2>(t);
+                top3v_merge<kQuadXor1>(t);
+                top3v_merge<kQuadXor2>(t);
                 const int nrep = (int)min(3u, end - start);
-                uint32_t kr0 = (uint32_t)t.key[0], kr1 = (uint32_t)t.key[1],
-                         kr2 = (uint32_t)t.key[2];
-                float cr0 = key_conf(t.key[0]), cr1 = key_conf(t.key[1]),
-                      cr2 = key_conf(t.key[2]);
-                if (t.tie) {
+                uint32_t kr0 = kPad, kr1 = kPad, kr2 = kPad;
+                float cr0 = o2f(t.t0), cr1 = o2f(t.t1), cr2 = o2f(t.t2);
+                if (!t.tie) {
+                    for (uint32_t k0 = start + q; k0 < end; k0 += 16u) {
+                        float cv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t k = k0 + 4u * u;
+                            cv[u] = k < end ? conf_at(k) : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t k = k0 + 4u * u;
+                            const uint32_t v = k < end ? conf_bits(cv[u]) : 0u;
+                            kr0 = (v != 0u && v == t.t0) ? k : kr0;
+                            kr1 = (v != 0u && v == t.t1) ? k : kr1;
+                            kr2 = (v != 0u && v == t.t2) ? k : kr2;
+                        }
+                    }
+                    kr0 = qmin<kQuadXor1>(kr0); kr0 = qmin<kQuadXor2>(kr0);
+                    kr1 = qmin<kQuadXor1>(kr1); kr1 = qmin<kQuadXor2>(kr1);
+                    kr2 = qmin<kQuadXor1>(kr2); kr2 = qmin<kQuadXor2>(kr2);
+                } else {
                     // equal confidences among the best: lane 0 ranks the whole cell in the
                     // full order (confidence, then position, then pixel id)
                     if (q == 0u) {
@@ -1880,16 +2010,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                             c.st = 0;
                             c.id = 0;
                             c.cam = 0;
-                            c.C = 1.0f;
-                            if (!no_mf) {
-                                if (have_cs) {
-                                    c.C = __uint_as_float(glob(C.conf_sorted)[k]);
-                                } else {
-                                    ensure_id(X, c);
-                                    const CamLite& cm = cams[c.cam];
-                                    c.C = glob(cm.conf)[c.id - cm.pix_off];
-                                }
-                            }
+                            c.C = no_mf ? 1.0f : conf_at(k);
                             top3_insert(X, rep, n, c);
                         }
                         kr0 = rep[0].k; cr0 = rep[0].C;
@@ -1904,7 +2025,12 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                     cr2 = qmovf<QuadBcast<0>::ctrl>(cr2);
                 }
                 if ((int)q < nrep) {
-                    st.sid[j * 3 + q] = q == 1u ? kr1 : (q == 2u ? kr2 : kr0);
+                    const uint32_t kq = q == 1u ? kr1 : (q == 2u ? kr2 : kr0);
+                    if (kq >= end) {                  // every value is some member's
+                        raise_error(bs, kErrBounds);
+                        st.bad[j] = 1;
+                    }
+                    st.sid[j * 3 + q] = kq < end ? kq : start;
                     st.sC[j * 3 + q] = q == 1u ? cr1 : (q == 2u ? cr2 : cr0);
                 }
                 if (fr_mids_any) {
@@ -1928,7 +2054,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
         }
         wave_sync();
         // ---- compaction of the representatives (lane = cell)
-        const uint32_t nrep_l = min(3u, st.end[lane] - st.start[lane]);
+        const uint32_t nrep_l = st.bad[lane] ? 0u : min(3u, st.end[lane] - st.start[lane]);
         const uint32_t incl = wave_incl(nrep_l);
         const uint32_t T = __shfl(incl, 63);
         for (uint32_t r = 0; r < nrep_l; ++r) st.list[incl - nrep_l + r] = (uint8_t)(lane * 3 + r);
@@ -1953,10 +2079,20 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                 continue;
             }
             ensure_p(X, mine);
-            const int f = last_le(sh.fpix, (int)nf, mine.id);
+            const uint32_t f = cm.frame;
             const DevFrame& fr = s_frames[f];
-            const double expo =
-                no_dc ? 0.0 : neg_log_v<KV>(cams, mine.cam, mine.p, fr.cam_begin, fr.n_cams, P);
+            double expo = 0.0;
+            if (!no_dc) {
+                uint64_t in_all = 0ull, partial = ~0ull;
+                if (!no_sa) {
+                    const CellCoord cc = coarse_cell(s_grids[f], mine.p);
+                    const auto kc = glob(C.cls) + ((uint64_t)f * G3 + cc.lin);
+                    in_all = kc->in_all;
+                    partial = kc->partial;
+                }
+                expo = neg_log_v<KV>(cams, cm.frame_cam, mine.p, fr.cam_begin, fr.n_cams,
+                                     in_all, partial, P);
+            }
             uint32_t rgb3 = 0;
             if (fr.rgb != nullptr && fr.has_rgb) {
                 const auto px = glob(cm.rgb + (uint64_t)(mine.id - cm.pix_off) * 3);
@@ -1980,7 +2116,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             if (nrep > 0 && !st.bad[j]) {
                 float Cr[3];
                 Pt pr[3];
-                double ex[3], wv[3];
+                double ex[3];
                 uint32_t c3[3], ids[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
@@ -1993,13 +2129,12 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                               : 0.0;
                     c3[r] = h ? st.rgb[sl] : 0u;
                     ids[r] = h ? st.sid[sl] : 0u;
-                    wv[r] = h ? (double)Cr[r] * exp(-ex[r]) : 0.0;
                 }
                 const int f = last_le(sh.fpix, (int)nf, ids[0]);
                 const DevFrame& fr = s_frames[f];
                 const uint32_t o = s - sh.cell_begin[f];
                 if (o < fr.capacity) {
-                    emit_cell(fr, o, nrep, Cr, pr, ex, wv, c3, ids, end - start);
+                    emit_cell(fr, o, nrep, Cr, pr, ex, c3, ids, end - start);
                     if (fr.moff) glob(fr.moff)[o] = start - sh.key_begin[f];
                     if (fr.keys) {
                         uint64_t key;
