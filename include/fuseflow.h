@@ -143,13 +143,15 @@ typedef struct ff_frame {
 
 typedef struct ff_context ff_context;
 
-/* Launch/tuning knobs of the device path (chosen by ff_autotune or set by hand). */
+/* Launch/tuning knobs of the device path (chosen by ff_autotune or set by hand).  None of
+ * them changes a result, only the time it takes. */
 typedef struct ff_tuning {
     int32_t radix_bits;           /* widest digit of the LSD radix sort, 6..10 (the key bits
                                      are spread evenly over the fewest passes) */
     int32_t sort_items;           /* keys per thread per sort tile: 8 or 16 */
-    int32_t cells_block;          /* reserved: the per-cell phase runs 256-thread workgroups
-                                     (read back as 256; any value in 64..1024 is accepted) */
+    int32_t hist_tiles;           /* 4096-pixel tiles per coarse-histogram workgroup: 1..8 */
+    int32_t cell_groups;          /* workgroups of the per-cell phase, 64..4096, or 0: as many
+                                     as are resident at once (1024), fewer for small batches */
     int32_t use_graph;            /* 1: ff_fuse_batch replays a cached HIP graph (default) */
 } ff_tuning;
 
@@ -182,13 +184,31 @@ ff_status ff_fuse(ff_context* ctx, int32_t n_cams, const ff_camera* cams,
 ff_status ff_fuse_batch(ff_context* ctx, int32_t n_frames, const ff_frame* frames,
                         const ff_params* params, const ff_output* outs, void* stream);
 
-/* Tuning: get/set the knobs; autotune times candidate settings on the given batch shape
- * (synchronises the stream) and keeps the fastest, cached by the resolution mix. */
+/* Tuning.  A context keeps a default tuning (get/set) and a cache of tunings keyed by the
+ * batch shape: the frames' camera resolutions in order, the grid and level limits, the
+ * flags and the view-list size.  A call uses the cached tuning of its shape, else the
+ * default.  ff_autotune times candidate settings on the given batch (one knob at a time:
+ * digit width x keys per thread, then histogram tiles, then per-cell workgroups; each
+ * candidate once untimed and three times timed, which synchronises the stream and leaves
+ * the batch's results in `outs`), caches the fastest for the batch's shape and returns
+ * it in *chosen. */
 ff_status ff_get_tuning(const ff_context* ctx, ff_tuning* t);
 ff_status ff_set_tuning(ff_context* ctx, const ff_tuning* t);
 ff_status ff_autotune(ff_context* ctx, int32_t n_frames, const ff_frame* frames,
                       const ff_params* params, const ff_output* outs, void* stream,
                       ff_tuning* chosen);
+/* The tuning cached for this batch's shape: *found = 1 and *t filled, or *found = 0. */
+ff_status ff_tuning_lookup(const ff_context* ctx, int32_t n_frames, const ff_frame* frames,
+                           const ff_params* params, ff_tuning* t, int32_t* found);
+/* The shape cache as JSON text ({"device": name, "entries": [{"shape": ..., knobs}, ...]}),
+ * for persisting it.  Writes at most cap bytes including the terminating zero into buf
+ * (buf may be NULL with cap 0) and the size it needs, terminating zero included, into
+ * *needed.  FF_ERR_INVALID_ARG when it does not fit. */
+ff_status ff_tuning_export(const ff_context* ctx, char* buf, uint64_t cap, uint64_t* needed);
+/* Merge entries of such a JSON text into the shape cache.  Entries recorded for another
+ * device name are skipped (*imported counts the rest); a malformed text or knob out of
+ * range gives FF_ERR_INVALID_ARG and changes nothing. */
+ff_status ff_tuning_import(ff_context* ctx, const char* json, int32_t* imported);
 
 /* Per-kernel timing.  While enabled, ff_fuse brackets every kernel it launches with HIP
  * events on the call's stream (ff_fuse_batch then launches directly instead of replaying a
@@ -296,6 +316,9 @@ typedef struct ff_server_config {
     int32_t max_pending;          /* submitted but not started frames; beyond: FF_ERR_BUSY */
     int32_t plain;                /* 1: baseline loop, one frame at a time through ff_fuse,
                                      the next frame starts after the previous completed */
+    int32_t autotune;             /* 1: the first batch of every new batch shape is autotuned
+                                     (ff_autotune on its lane, which holds the scheduler for
+                                     the search) and the tuning is shared by all lanes */
 } ff_server_config;
 
 typedef struct ff_stats {
@@ -309,7 +332,8 @@ typedef struct ff_stats {
     double mean_batch_frames;
 } ff_stats;
 
-/* Defaults: 2 lanes, 16 frames per batch, 256 cameras, 4096 pending, not plain. */
+/* Defaults: 2 lanes, 16 frames per batch, 256 cameras, 4096 pending, not plain, no
+ * autotuning. */
 void ff_server_config_default(ff_server_config* cfg);
 
 /* Creates the lanes.  Each lane's workspace takes at most budget / lanes bytes; frames larger

@@ -61,7 +61,8 @@ class ff_frame(ctypes.Structure):
 
 class ff_tuning(ctypes.Structure):
     _fields_ = [("radix_bits", ctypes.c_int32), ("sort_items", ctypes.c_int32),
-                ("cells_block", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("hist_tiles", ctypes.c_int32), ("cell_groups", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class ff_trace(ctypes.Structure):
@@ -87,7 +88,8 @@ class ff_emc_params(ctypes.Structure):
 class ff_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("lanes", ctypes.c_int32),
                 ("max_batch_frames", ctypes.c_int32), ("max_cameras", ctypes.c_int32),
-                ("max_pending", ctypes.c_int32), ("plain", ctypes.c_int32)]
+                ("max_pending", ctypes.c_int32), ("plain", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class ff_stats(ctypes.Structure):
@@ -120,6 +122,13 @@ EXPORTS = {
     "ff_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
                                    ctypes.POINTER(ff_params), ctypes.POINTER(ff_output),
                                    ctypes.c_void_p, ctypes.POINTER(ff_tuning)]),
+    "ff_tuning_lookup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
+                                        ctypes.POINTER(ff_params), ctypes.POINTER(ff_tuning),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "ff_tuning_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "ff_tuning_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p,
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "ff_trace_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ff_trace_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_trace)]),
     "ff_trace_slot_name": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -443,6 +452,38 @@ class Context:
         r = res.cpu().tolist()
         return dict(emc_m=r[0], points=int(round(r[1])), mean_visible=r[2])
 
+    def tuning_for(self, frames: List[Dict], params: Optional[Params] = None) -> Optional[Dict]:
+        """The tuning cached for this batch shape, or None."""
+        cf, keep = self._frames(frames)
+        t, found = ff_tuning(), ctypes.c_int32()
+        _check(_lib.ff_tuning_lookup(self.h, len(frames), cf, ctypes.byref((params or Params()).c),
+                                     ctypes.byref(t), ctypes.byref(found)), "ff_tuning_lookup")
+        return {k: getattr(t, k) for k, _ in ff_tuning._fields_} if found.value else None
+
+    def export_tuning(self) -> str:
+        """The per-shape tuning cache as JSON text (ff_tuning_export)."""
+        need = ctypes.c_uint64()
+        _lib.ff_tuning_export(self.h, None, 0, ctypes.byref(need))
+        buf = ctypes.create_string_buffer(int(need.value))
+        _check(_lib.ff_tuning_export(self.h, buf, need.value, ctypes.byref(need)),
+               "ff_tuning_export")
+        return buf.value.decode()
+
+    def import_tuning(self, text: str) -> int:
+        """Merge a JSON tuning cache (entries of other devices are skipped); returns the
+        number of entries taken."""
+        n = ctypes.c_int32()
+        _check(_lib.ff_tuning_import(self.h, text.encode(), ctypes.byref(n)), "ff_tuning_import")
+        return int(n.value)
+
+    def save_tuning(self, path: str):
+        with open(path, "w") as f:
+            f.write(self.export_tuning())
+
+    def load_tuning(self, path: str) -> int:
+        with open(path) as f:
+            return self.import_tuning(f.read())
+
     def autotune(self, frames: List[Dict], params: Optional[Params] = None,
                  outs: Optional[List[Output]] = None, stream=None) -> Dict:
         cf, keep = self._frames(frames)
@@ -465,7 +506,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 16 << 30, lanes: int = 2,
                  max_batch_frames: int = 16, max_cameras: int = 256, max_pending: int = 4096,
-                 plain: bool = False, device: Optional[int] = None):
+                 plain: bool = False, autotune: bool = False, device: Optional[int] = None):
         torch = _torch()
         if device is None:
             device = torch.cuda.current_device()
@@ -474,6 +515,7 @@ class Server:
         cfg.hbm_budget_bytes, cfg.lanes = int(hbm_budget_bytes), int(lanes)
         cfg.max_batch_frames, cfg.max_cameras = int(max_batch_frames), int(max_cameras)
         cfg.max_pending, cfg.plain = int(max_pending), int(bool(plain))
+        cfg.autotune = int(bool(autotune))
         h = ctypes.c_void_p()
         _check(_lib.ff_server_create(ctypes.byref(h), device, ctypes.byref(cfg)), "ff_server_create")
         self.h = h

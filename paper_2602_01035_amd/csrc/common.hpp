@@ -104,6 +104,7 @@ struct CallHdr {
     uint32_t any_mids;
     uint32_t key64_ok;               // the key-width bound allows keys wider than 32 bits
     uint32_t cls_lanes;              // log2 of the camera slots per coarse cell (class phase)
+    uint32_t hist_tiles;             // pixel tiles per coarse-histogram workgroup
 };
 
 // Field-of-view class of every camera of a frame for one occupied coarse cell: bit j of
@@ -150,7 +151,7 @@ enum PhaseKind : uint32_t {
 };
 
 constexpr int kEmcBlocks = 2048;         // workgroups of the E_MC evaluator
-constexpr int kHistTiles = 4;            // pixel tiles per coarse-histogram workgroup
+constexpr int kMaxHistTiles = 8;         // pixel tiles per coarse-histogram workgroup (tuned)
 
 // trace slots of the Eq. 3 confidence phase and of the camera classes (the radix passes
 // use 16 .. 30; slots 7 .. 9 are not used by the radix kinds, which map to 16 ..)

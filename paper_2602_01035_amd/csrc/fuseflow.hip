@@ -241,7 +241,9 @@ struct ff_context {
     hipEvent_t last = nullptr;
     bool have_last = false;
     std::vector<void*> allocs;
-    ff_tuning tune{8, 8, 256, 1};
+    ff_tuning tune{8, 8, 4, 0, 1};                // default tuning
+    std::map<std::string, ff_tuning> tuned;       // tuning per batch shape
+    std::string device_name;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graphs;
     // kernel tracing (events on the call's stream)
@@ -406,6 +408,39 @@ ff_status grow_counts(ff_context* c, uint64_t need, hipStream_t stream) {
     return FF_OK;
 }
 
+// The key of a batch shape in the tuning cache: every frame's camera resolutions in order,
+// the grid and level limits, the flags and the view-list size.  Empty when the batch is not
+// well formed (the call itself then reports the error).
+std::string shape_key(int32_t n_frames, const ff_frame* frames, const ff_params* prm) {
+    std::string k;
+    if (n_frames < 1 || !frames || !prm) return k;
+    char buf[96];
+    for (int32_t f = 0; f < n_frames; ++f) {
+        if (frames[f].n_cams < 1 || !frames[f].cams) return std::string();
+        for (int32_t i = 0; i < frames[f].n_cams; ++i) {
+            std::snprintf(buf, sizeof(buf), "%dx%d,", frames[f].cams[i].width, frames[f].cams[i].height);
+            k += buf;
+        }
+        k += ";";
+    }
+    std::snprintf(buf, sizeof(buf), "|G%d|L%d|f%u|w%d", prm->coarse_res, prm->max_level,
+                  prm->flags, prm->k_views > 4 ? 1 : 0);
+    return k + buf;
+}
+
+bool tuning_ok(const ff_tuning& t) {
+    return t.radix_bits >= 6 && t.radix_bits <= kMaxRadixBits &&
+           (t.sort_items == 8 || t.sort_items == 16) && t.hist_tiles >= 1 &&
+           t.hist_tiles <= kMaxHistTiles && (t.cell_groups == 0 ||
+           (t.cell_groups >= 64 && t.cell_groups <= 4096)) &&
+           (t.use_graph == 0 || t.use_graph == 1);
+}
+
+const ff_tuning& tuning_for(const ff_context* c, const std::string& key) {
+    auto it = c->tuned.find(key);
+    return it == c->tuned.end() ? c->tune : it->second;
+}
+
 Ctx make_ctx(ff_context* c) {
     Ctx C;
     C.hdr = reinterpret_cast<const CallHdr*>(c->d_desc);
@@ -444,6 +479,7 @@ struct Launch {
 };
 struct Plan {
     std::vector<Launch> launches;
+    int sort_items = 8;         // keys per thread of the sort tiles
     uint32_t ncams = 0;
     bool wide_views = false;    // K - 1 > 3 kept views
     size_t desc_used = 0;       // bytes of the descriptor this call fills
@@ -455,8 +491,8 @@ struct Plan {
 // Validate one batch and fill the host staging descriptor.  Returns the launch plan and a
 // key describing everything the plan depends on (for the graph cache).
 ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
-                     const ff_params* prm, const ff_output* outs, char* stage, Plan& plan,
-                     std::string& shape) {
+                     const ff_params* prm, const ff_output* outs, const ff_tuning& T,
+                     char* stage, Plan& plan, std::string& shape) {
     if (n_frames < 1 || n_frames > c->max_frames || !frames || !outs) return FF_ERR_INVALID_ARG;
     ff_status st = validate_params(prm);
     if (st != FF_OK) return st;
@@ -556,7 +592,8 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     plan.ncams = ncam;
     plan.nframes = (uint32_t)n_frames;
     plan.wide_views = prm->k_views > 4;
-    plan.radix_bits = c->tune.radix_bits;
+    plan.radix_bits = T.radix_bits;
+    plan.sort_items = T.sort_items;
     H->n_px_tiles = ntile;
     plan.desc_used = tc_off + 2 * (size_t)ntile;
     H->P_tot = (uint32_t)P;
@@ -564,13 +601,16 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     const uint64_t ncounts = no_sa ? 0 : (uint64_t)n_frames * G3;
     H->n_counts = (uint32_t)ncounts;
     H->n_scan_tiles = (uint32_t)std::max<uint64_t>(1, (ncounts + kScanTile - 1) / kScanTile);
-    const uint32_t KT = (uint32_t)(kBlock * c->tune.sort_items);
-    H->sort_items = (uint32_t)c->tune.sort_items;
+    const uint32_t KT = (uint32_t)(kBlock * T.sort_items);
+    H->sort_items = (uint32_t)T.sort_items;
+    H->hist_tiles = (uint32_t)T.hist_tiles;
     H->n_sort_tiles = (uint32_t)std::max<uint64_t>(1, (P + KT - 1) / KT);
     // per-cell phase: waves walk 64-cell steps; at most the workgroups that fit resident
     // at once (4 per CU at its register use), so no partial second round trails the launch
-    H->n_cell_items = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096));
-    H->max_radix_bits = (uint32_t)c->tune.radix_bits;
+    H->n_cell_items = T.cell_groups > 0
+                          ? (uint32_t)T.cell_groups
+                          : (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096));
+    H->max_radix_bits = (uint32_t)T.radix_bits;
     // Widest possible dense key.  The key range T is the sum over occupied coarse cells of
     // 8^L.  A cell refined to level L >= 1 holds more than target 4^(L-1) points (level L-1
     // did not suffice), so it spends fewer than 2^(L+2) / target key values per point; a
@@ -604,7 +644,7 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     add(PH_BACKPROJECT, ntile, 0);
     add(PH_TILE_REDUCE, (uint32_t)n_frames, 0);
     if (!no_sa) {
-        add(PH_HIST, (ntile + kHistTiles - 1) / kHistTiles, 0);
+        add(PH_HIST, (ntile + H->hist_tiles - 1) / H->hist_tiles, 0);
         add(PH_SCAN_A, H->n_scan_tiles, 0);
         add(PH_SCAN_M, 1, 0);
         add(PH_SCAN_B, H->n_scan_tiles, 0);
@@ -636,9 +676,9 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     // and level limits, flags, the per-cell kernel variant, tuning, and the sort's pass
     // count and key width (set by the level limits and the target count through the
     // key-width bound; the key width sizes the scatter's LDS)
-    std::snprintf(tail, sizeof(tail), "|G%d|L%d|f%u|w%d|t%d,%d|p%u,%u", G, prm->max_level,
-                  prm->flags, plan.wide_views ? 1 : 0, c->tune.radix_bits, c->tune.sort_items,
-                  H->npass_max, H->key64_ok);
+    std::snprintf(tail, sizeof(tail), "|G%d|L%d|f%u|w%d|t%d,%d,%d,%d|p%u,%u", G, prm->max_level,
+                  prm->flags, plan.wide_views ? 1 : 0, T.radix_bits, T.sort_items,
+                  T.hist_tiles, T.cell_groups, H->npass_max, H->key64_ok);
     shape += tail;
     return FF_OK;
 }
@@ -785,7 +825,7 @@ ff_status run_plain(ff_context* c, const Ctx& C, const Plan& plan, hipStream_t s
 }
 
 ff_status dispatch_plain(ff_context* c, const Ctx& C, const Plan& plan, hipStream_t s) {
-    switch (c->tune.sort_items) {
+    switch (plan.sort_items) {
         case 16: return run_plain<16>(c, C, plan, s);
         default: return run_plain<8>(c, C, plan, s);
     }
@@ -948,6 +988,15 @@ ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
     c->max_pixels = max_pixels;
     c->max_cams = max_cameras;
     c->max_frames = max_frames;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            c->device_name = prop.name;
+            for (char& ch : c->device_name)
+                if (ch == '"' || ch == '\\') ch = ' ';
+        }
+        if (c->device_name.empty()) c->device_name = "unknown";
+    }
     const Sizes s = sizes_for(max_pixels, max_cameras, max_frames);
     c->desc_bytes = s.desc;
     ff_status st = FF_OK;
@@ -1001,14 +1050,8 @@ ff_status ff_get_tuning(const ff_context* c, ff_tuning* t) {
 }
 
 ff_status ff_set_tuning(ff_context* c, const ff_tuning* t) {
-    if (!c || !t) return FF_ERR_INVALID_ARG;
-    if (t->radix_bits < 6 || t->radix_bits > kMaxRadixBits) return FF_ERR_INVALID_ARG;
-    if (t->sort_items != 8 && t->sort_items != 16) return FF_ERR_INVALID_ARG;
-    if (t->cells_block < 64 || t->cells_block > 1024 || (t->use_graph != 0 && t->use_graph != 1))
-        return FF_ERR_INVALID_ARG;
-    if (t->radix_bits != c->tune.radix_bits || t->sort_items != c->tune.sort_items) drop_graphs(c);
-    c->tune = *t;
-    c->tune.cells_block = kBlock;   // the per-cell phase runs at the common block size
+    if (!c || !t || !tuning_ok(*t)) return FF_ERR_INVALID_ARG;
+    c->tune = *t;              // cached graphs are keyed by their tuning: none goes stale
     return FF_OK;
 }
 
@@ -1029,7 +1072,8 @@ static ff_status fuse_impl(ff_context* c, int32_t n_frames, const ff_frame* fram
     FF_HIP(hipEventSynchronize(c->stage_ev[slot]));
     Plan plan;
     std::string shape;
-    ff_status st = build_desc(c, n_frames, frames, params, outs, c->h_stage[slot], plan, shape);
+    const ff_tuning T = tuning_for(c, shape_key(n_frames, frames, params));
+    ff_status st = build_desc(c, n_frames, frames, params, outs, T, c->h_stage[slot], plan, shape);
     if (st != FF_OK) return st;
     if (c->trace && (st = trace_collect(c)) != FF_OK) return st;
     if (!c->probe_pending.empty() &&
@@ -1040,7 +1084,7 @@ static ff_status fuse_impl(ff_context* c, int32_t n_frames, const ff_frame* fram
     if (c->have_last) FF_HIP(hipStreamWaitEvent(s, c->last, 0));
     FF_HIP(hipMemcpyAsync(c->d_desc, c->h_stage[slot], plan.desc_used, hipMemcpyHostToDevice, s));
     FF_HIP(hipEventRecord(c->stage_ev[slot], s));
-    const bool graph = batched && c->tune.use_graph && !c->trace;
+    const bool graph = batched && T.use_graph && !c->trace;
     if (c->probe_slot >= 0 && !c->trace) {
         uint64_t px = 0;
         for (int32_t f = 0; f < n_frames; ++f)
@@ -1280,43 +1324,185 @@ ff_status ff_autotune(ff_context* c, int32_t n_frames, const ff_frame* frames,
                       const ff_params* params, const ff_output* outs, void* stream,
                       ff_tuning* chosen) {
     if (!c) return FF_ERR_INVALID_ARG;
+    const std::string key = shape_key(n_frames, frames, params);
+    if (key.empty()) return FF_ERR_INVALID_ARG;
     DeviceGuard g(c->device);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const ff_tuning keep = c->tune;
-    ff_tuning best = keep;
-    float best_ms = 1e30f;
+    const bool had = c->tuned.count(key) != 0;
+    const ff_tuning keep = tuning_for(c, key);
     hipEvent_t e0, e1;
     FF_HIP(hipEventCreate(&e0));
-    FF_HIP(hipEventCreate(&e1));
-    const int bits[] = {6, 7, 8, 9, 10};
-    const int items[] = {8, 16};
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FF_ERR_HIP;
+    }
     ff_status st = FF_OK;
-    for (int b : bits) {
-        for (int it : items) {
-            ff_tuning t = keep;
+    // one untimed and three timed calls of the batch with candidate t cached for its shape
+    auto time_of = [&](const ff_tuning& t, float& ms) -> ff_status {
+        c->tuned[key] = t;
+        ff_status r = ff_fuse_batch(c, n_frames, frames, params, outs, stream);
+        if (r != FF_OK) return r;
+        FF_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < 3 && r == FF_OK; ++i)
+            r = ff_fuse_batch(c, n_frames, frames, params, outs, stream);
+        if (r != FF_OK) return r;
+        FF_HIP(hipEventRecord(e1, s));
+        FF_HIP(hipEventSynchronize(e1));
+        FF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return FF_OK;
+    };
+    ff_tuning best = keep;
+    float best_ms = 1e30f;
+    // one knob at a time: digit width x keys per thread, then histogram tiles per
+    // workgroup, then per-cell workgroups
+    for (int b : {6, 7, 8, 9, 10}) {
+        for (int it : {8, 16}) {
+            ff_tuning t = best;
             t.radix_bits = b;
             t.sort_items = it;
-            if ((st = ff_set_tuning(c, &t)) != FF_OK) break;
-            if ((st = ff_fuse_batch(c, n_frames, frames, params, outs, stream)) != FF_OK) break;
-            if (hipEventRecord(e0, s) != hipSuccess) { st = FF_ERR_HIP; break; }
-            const int reps = 3;
-            for (int r = 0; r < reps && st == FF_OK; ++r)
-                st = ff_fuse_batch(c, n_frames, frames, params, outs, stream);
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                st = FF_ERR_HIP;
-                break;
-            }
-            float ms = 0;
-            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = FF_ERR_HIP; break; }
-            if (st == FF_OK && ms < best_ms) { best_ms = ms; best = t; }
+            float ms = 0.0f;
+            if ((st = time_of(t, ms)) != FF_OK) break;
+            if (ms < best_ms) { best_ms = ms; best = t; }
         }
         if (st != FF_OK) break;
     }
+    const ff_tuning after_sort = best;
+    for (int h : {1, 2, 4, 8}) {
+        if (st != FF_OK) break;
+        ff_tuning t = after_sort;
+        t.hist_tiles = h;
+        float ms = 0.0f;
+        if ((st = time_of(t, ms)) != FF_OK) break;
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    const ff_tuning after_hist = best;
+    for (int cg : {0, 512, 768, 1536, 2048}) {
+        if (st != FF_OK) break;
+        ff_tuning t = after_hist;
+        t.cell_groups = cg;
+        float ms = 0.0f;
+        if ((st = time_of(t, ms)) != FF_OK) break;
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)ff_set_tuning(c, st == FF_OK ? &best : &keep);
-    if (chosen) *chosen = c->tune;
+    if (st == FF_OK) {
+        c->tuned[key] = best;
+    } else if (had) {
+        c->tuned[key] = keep;
+    } else {
+        c->tuned.erase(key);
+    }
+    if (chosen) *chosen = st == FF_OK ? best : keep;
     return st;
+}
+
+}  // extern "C"
+
+void ff::share_tuning(const ff_context* src, ff_context* dst) {
+    if (!src || !dst || src == dst) return;
+    for (const auto& kv : src->tuned) dst->tuned[kv.first] = kv.second;
+}
+
+extern "C" {
+
+ff_status ff_tuning_lookup(const ff_context* c, int32_t n_frames, const ff_frame* frames,
+                           const ff_params* params, ff_tuning* t, int32_t* found) {
+    if (!c || !t || !found) return FF_ERR_INVALID_ARG;
+    const std::string key = shape_key(n_frames, frames, params);
+    if (key.empty()) return FF_ERR_INVALID_ARG;
+    auto it = c->tuned.find(key);
+    *found = it != c->tuned.end() ? 1 : 0;
+    if (*found) *t = it->second;
+    return FF_OK;
+}
+
+ff_status ff_tuning_export(const ff_context* c, char* buf, uint64_t cap, uint64_t* needed) {
+    if (!c || !needed || (cap > 0 && !buf)) return FF_ERR_INVALID_ARG;
+    std::string j = "{\"device\": \"" + c->device_name + "\", \"entries\": [";
+    char tmp[160];
+    bool first = true;
+    for (const auto& kv : c->tuned) {
+        const ff_tuning& t = kv.second;
+        std::snprintf(tmp, sizeof(tmp),
+                      "\", \"radix_bits\": %d, \"sort_items\": %d, \"hist_tiles\": %d, "
+                      "\"cell_groups\": %d, \"use_graph\": %d}",
+                      t.radix_bits, t.sort_items, t.hist_tiles, t.cell_groups, t.use_graph);
+        j += std::string(first ? "" : ", ") + "{\"shape\": \"" + kv.first + tmp;
+        first = false;
+    }
+    j += "]}";
+    *needed = j.size() + 1;
+    if (cap < j.size() + 1) return FF_ERR_INVALID_ARG;
+    std::memcpy(buf, j.c_str(), j.size() + 1);
+    return FF_OK;
+}
+
+namespace {
+
+// the string value following "name": in text at or after pos (no escapes: device names
+// and shape keys contain none); npos when absent
+size_t json_string(const std::string& text, const char* name, size_t pos, std::string& out) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t k = text.find(pat, pos);
+    if (k == std::string::npos) return k;
+    k = text.find(':', k + pat.size());
+    if (k == std::string::npos) return k;
+    k = text.find('"', k);
+    if (k == std::string::npos) return k;
+    const size_t e = text.find('"', k + 1);
+    if (e == std::string::npos) return e;
+    out = text.substr(k + 1, e - k - 1);
+    return e + 1;
+}
+
+bool json_int(const std::string& obj, const char* name, int32_t& out) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t k = obj.find(pat);
+    if (k == std::string::npos) return false;
+    k = obj.find(':', k + pat.size());
+    if (k == std::string::npos) return false;
+    char* end = nullptr;
+    const long v = std::strtol(obj.c_str() + k + 1, &end, 10);
+    if (end == obj.c_str() + k + 1 || v < -1000000 || v > 1000000) return false;
+    out = (int32_t)v;
+    return true;
+}
+
+}  // namespace
+
+ff_status ff_tuning_import(ff_context* c, const char* json, int32_t* imported) {
+    if (!c || !json) return FF_ERR_INVALID_ARG;
+    const std::string text(json);
+    std::string dev;
+    if (json_string(text, "device", 0, dev) == std::string::npos) return FF_ERR_INVALID_ARG;
+    size_t pos = text.find("\"entries\"");
+    if (pos == std::string::npos) return FF_ERR_INVALID_ARG;
+    std::vector<std::pair<std::string, ff_tuning>> got;
+    while (true) {
+        const size_t ob = text.find('{', pos);
+        if (ob == std::string::npos) break;
+        const size_t cb = text.find('}', ob);
+        if (cb == std::string::npos) return FF_ERR_INVALID_ARG;
+        const std::string obj = text.substr(ob, cb - ob + 1);
+        std::string shape;
+        ff_tuning t{};
+        if (json_string(obj, "shape", 0, shape) == std::string::npos ||
+            !json_int(obj, "radix_bits", t.radix_bits) || !json_int(obj, "sort_items", t.sort_items) ||
+            !json_int(obj, "hist_tiles", t.hist_tiles) ||
+            !json_int(obj, "cell_groups", t.cell_groups) || !json_int(obj, "use_graph", t.use_graph) ||
+            !tuning_ok(t) || shape.empty())
+            return FF_ERR_INVALID_ARG;
+        got.emplace_back(shape, t);
+        pos = cb + 1;
+    }
+    int32_t n = 0;
+    if (dev == c->device_name) {
+        for (const auto& e : got) c->tuned[e.first] = e.second;
+        n = (int32_t)got.size();
+    }
+    if (imported) *imported = n;
+    return FF_OK;
 }
 
 }  // extern "C"

@@ -9,4 +9,7 @@ namespace ff {
 // colour on every view when colour is asked for.  FF_OK or FF_ERR_INVALID_ARG.
 ff_status check_frame(const ff_frame& fr, const ff_params& prm, const ff_output& out);
 
+// Copy every per-shape tuning of src into dst (contexts of one process).
+void share_tuning(const ff_context* src, ff_context* dst);
+
 }  // namespace ff

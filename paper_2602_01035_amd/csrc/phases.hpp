@@ -803,8 +803,8 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem)
     const uint64_t G3 = (uint64_t)(P.G * P.G * P.G);
     // this workgroup's tiles share one LDS hash; it goes out to the frame's counts (one
     // global atomic per distinct cell) when the frame changes and at the end
-    const uint32_t t0 = item * kHistTiles;
-    const uint32_t t1 = min(t0 + (uint32_t)kHistTiles, H.n_px_tiles);
+    const uint32_t t0 = item * H.hist_tiles;
+    const uint32_t t1 = min(t0 + H.hist_tiles, H.n_px_tiles);
     if (t0 >= t1) return;
     uint32_t frame = C.cams[cam_of_tile(C, t0)].frame;
     auto flush = [&](uint32_t f) {
@@ -823,7 +823,7 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem)
     const DevCam* cur = &C.cams[cam_of_tile(C, t0)];
     load_tile(*cur, t0, buf[0]);
 #pragma unroll
-    for (int i = 0; i < kHistTiles; ++i) {
+    for (int i = 0; i < kMaxHistTiles; ++i) {
         const uint32_t tile = t0 + (uint32_t)i;
         if (tile >= t1) break;
         const DevCam& cm = *cur;

@@ -147,6 +147,19 @@ bool ff_server::launch(Lane& L, double t) {
         if (st == FF_OK && hipStreamWaitEvent(L.stream, L.batch[i].ready, 0) != hipSuccess)
             st = FF_ERR_HIP;
     }
+    if (st == FF_OK && cfg.autotune && !cfg.plain) {
+        // the first batch of a new shape: tune it on this lane, share with the others
+        ff_tuning t;
+        int32_t found = 0;
+        st = ff_tuning_lookup(L.ctx, (int32_t)frames.size(), frames.data(), &L.batch[0].params,
+                              &t, &found);
+        if (st == FF_OK && !found) {
+            st = ff_autotune(L.ctx, (int32_t)frames.size(), frames.data(), &L.batch[0].params,
+                             outs.data(), L.stream, &t);
+            if (st == FF_OK)
+                for (Lane& o : lanes) ff::share_tuning(L.ctx, o.ctx);
+        }
+    }
     if (st == FF_OK) {
         if (cfg.plain)
             st = ff_fuse(L.ctx, frames[0].n_cams, frames[0].cams, frames[0].views,
@@ -261,6 +274,7 @@ void ff_server_config_default(ff_server_config* c) {
     c->max_cameras = 256;
     c->max_pending = 4096;
     c->plain = 0;
+    c->autotune = 0;
 }
 
 ff_status ff_server_create(ff_server** out, int device, const ff_server_config* cfg) {

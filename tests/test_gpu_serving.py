@@ -92,16 +92,82 @@ def test_graph_replay_follows_key_width(ff):
 
 @pytest.mark.parametrize("tuning", [dict(radix_bits=6, sort_items=8),
                                     dict(radix_bits=8, sort_items=16),
-                                    dict(radix_bits=10, sort_items=8)])
+                                    dict(radix_bits=10, sort_items=8),
+                                    dict(hist_tiles=1), dict(hist_tiles=3), dict(hist_tiles=8),
+                                    dict(cell_groups=64), dict(cell_groups=777),
+                                    dict(cell_groups=4096),
+                                    dict(radix_bits=7, sort_items=16, hist_tiles=2,
+                                         cell_groups=300, use_graph=0)])
 def test_tuning_does_not_change_results(ff, tuning):
+    """Every knob of the tuning changes only the launch shapes: results equal the oracle's,
+    plain and batched."""
     print(f"[case] tuning {tuning}", flush=True)
     f = cached_frame("c2")
     d = ff.to_device(f)
-    ctx = ff.Context(max_pixels=2_000_000, max_cameras=8, max_frames=2)
+    ctx = ff.Context(max_pixels=4_000_000, max_cameras=8, max_frames=2)
     ctx.set_tuning(**tuning)
-    g = ctx.fuse_batch([d])[0].result()
-    compare(g, O.fuse_frame(f), label=str(tuning))
+    o = O.fuse_frame(f)
+    compare(ctx.fuse_batch([d])[0].result(), o, label=f"batched {tuning}")
+    compare(ctx.fuse(d["cams"], d["depth"], d["conf"], d["rgb"]).result(), o,
+            check_members=False, label=f"plain {tuning}")
+    outs = ctx.fuse_batch([d, d])
+    for out in outs:
+        compare(out.result(), o, check_members=False, label=f"batch of two {tuning}")
     ctx.close()
+
+
+def test_autotune_caches_per_shape_and_persists(ff, tmp_path):
+    """ff_autotune caches its choice for the batch's shape only; the cache survives a JSON
+    round trip into a fresh context and ignores entries of another device; a malformed
+    text is refused.  Tuned calls keep the oracle's results."""
+    print("[case] autotune cache", flush=True)
+    f1, f2 = cached_frame("c1"), cached_frame("c2")
+    d1, d2 = ff.to_device(f1), ff.to_device(f2)
+    ctx = ff.Context(max_pixels=4_000_000, max_cameras=8, max_frames=2)
+    assert ctx.tuning_for([d1]) is None and ctx.tuning_for([d2]) is None
+    chosen = ctx.autotune([d1])
+    assert ctx.tuning_for([d1]) == chosen
+    assert ctx.tuning_for([d2]) is None and ctx.tuning_for([d1, d1]) is None
+    compare(ctx.fuse_batch([d1])[0].result(), O.fuse_frame(f1), label="tuned c1")
+    text = ctx.export_tuning()
+    assert '"entries"' in text and f1.cams[0].width.__str__() in text
+    path = tmp_path / "tuning.json"
+    ctx.save_tuning(str(path))
+    fresh = ff.Context(max_pixels=4_000_000, max_cameras=8, max_frames=2)
+    assert fresh.load_tuning(str(path)) == 1
+    assert fresh.tuning_for([d1]) == chosen
+    import json
+    other = json.loads(text)
+    other["device"] = "some other device"
+    other["entries"][0]["shape"] = "1x1,;|G64|L6|f0|w0"
+    assert fresh.import_tuning(json.dumps(other)) == 0
+    with pytest.raises(ff.FuseFlowError):
+        fresh.import_tuning('{"device": "x", "entries": [{"shape": "1x1,;", "radix_bits": 99}]}')
+    compare(fresh.fuse_batch([d1])[0].result(), O.fuse_frame(f1), label="imported tuning")
+    fresh.close()
+    ctx.close()
+
+
+def test_server_autotunes_each_new_shape(ff):
+    """A server with autotuning tunes the first batch of each shape and shares the tuning
+    between lanes; results stay identical to ff_fuse."""
+    print("[case] server autotune", flush=True)
+    frames = [cached_frame("c1"), cached_frame("c2")]
+    devs = [ff.to_device(f) for f in frames]
+    alone = [_alone(ff, d) for d in devs]
+    srv = ff.Server(hbm_budget_bytes=2 << 30, lanes=2, max_batch_frames=1, autotune=True)
+    outs = []
+    for rep in range(3):
+        for i, d in enumerate(devs):
+            out = ff.Output(sum(c.width * c.height for c in d["cams"]), rgb=True)
+            srv.submit(i, d, out)
+            outs.append((i, out))
+    srv.drain()
+    for i, out in outs:
+        g = out.result()
+        for k in KEYS:
+            assert np.array_equal(g[k], alone[i][k]), (i, k)
+    srv.close()
 
 
 @pytest.mark.parametrize("plain", [False, True])
