@@ -309,7 +309,9 @@ ff_status ff_emc_noalloc(int32_t n_cams, const ff_camera* cams, const ff_view* v
 typedef struct ff_server ff_server;
 
 typedef struct ff_server_config {
-    uint64_t hbm_budget_bytes;    /* device memory for all lane workspaces together */
+    uint64_t hbm_budget_bytes;    /* device memory for all lane workspaces together: frames
+                                     are admitted by their workspace footprint against what
+                                     the running batches leave of it */
     int32_t lanes;                /* concurrent batches (one stream + workspace each), 1..8 */
     int32_t max_batch_frames;     /* frames per batch, 1..64 */
     int32_t max_cameras;          /* cameras per batch, 1..1024 */
@@ -330,20 +332,27 @@ typedef struct ff_stats {
     double p50_ms, p99_ms, mean_ms, max_ms;   /* frame latency: completion - arrival */
     double px_per_s;              /* pixels / (last_done - first_arrival) */
     double mean_batch_frames;
+    uint64_t hbm_used_bytes;      /* device bytes of the lanes' workspaces now */
+    uint64_t hbm_peak_bytes;      /* and at most so far (never above the budget) */
 } ff_stats;
 
 /* Defaults: 2 lanes, 16 frames per batch, 256 cameras, 4096 pending, not plain, no
  * autotuning. */
 void ff_server_config_default(ff_server_config* cfg);
 
-/* Creates the lanes.  Each lane's workspace takes at most budget / lanes bytes; frames larger
- * than a lane can hold are refused at submit with FF_ERR_OOM.  FF_ERR_OOM here if not even
- * one 4096-pixel frame fits. */
+/* Creates the lanes (streams); their workspaces are made when a lane first takes a batch,
+ * sized by it (ff_workspace_bytes of the batch's pixels, cameras and frames), and grown
+ * when a later batch needs more.  The workspaces of all lanes together never exceed the
+ * budget: a frame joins a batch only while the batch still fits what the other lanes leave,
+ * otherwise it waits (FIFO) until running batches complete; idle lanes give their
+ * workspaces back when the next frame fits nowhere else.  A frame whose own workspace
+ * exceeds the whole budget is refused at submit with FF_ERR_OOM.  FF_ERR_OOM here if not
+ * even one 4096-pixel frame fits. */
 ff_status ff_server_create(ff_server** out, int device, const ff_server_config* cfg);
 void ff_server_destroy(ff_server* s);
 
-/* Largest frame (pixels) one lane admits. */
-uint64_t ff_server_lane_pixels(const ff_server* s);
+/* Largest single frame (pixels, with the configured camera limit) the budget admits. */
+uint64_t ff_server_max_pixels(const ff_server* s);
 
 /* Seconds on the server clock (steady clock, zero at creation). */
 double ff_server_now(const ff_server* s);
@@ -355,7 +364,7 @@ double ff_server_now(const ff_server* s);
  * is complete before the frame is read.  The host structs are copied; the device images
  * and `out` buffers must stay valid until the frame is done.  Returns, for this frame
  * only: FF_ERR_INVALID_ARG when the host checks of ff_fuse_batch reject it, FF_ERR_OOM
- * when it is larger than a lane, FF_ERR_BUSY when max_pending frames wait already.
+ * when its workspace exceeds the budget, FF_ERR_BUSY when max_pending frames wait already.
  * Nothing about one frame affects the acceptance of other frames. */
 ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
                            const ff_params* params, const ff_output* out, double arrival_s,

@@ -98,7 +98,8 @@ class ff_stats(ctypes.Structure):
                 ("last_done_s", ctypes.c_double), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("px_per_s", ctypes.c_double),
-                ("mean_batch_frames", ctypes.c_double)]
+                ("mean_batch_frames", ctypes.c_double), ("hbm_used_bytes", ctypes.c_uint64),
+                ("hbm_peak_bytes", ctypes.c_uint64)]
 
 
 # ----------------------------------------------------------------------------- library
@@ -151,7 +152,7 @@ EXPORTS = {
     "ff_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                         ctypes.POINTER(ff_server_config)]),
     "ff_server_destroy": (None, [ctypes.c_void_p]),
-    "ff_server_lane_pixels": (ctypes.c_uint64, [ctypes.c_void_p]),
+    "ff_server_max_pixels": (ctypes.c_uint64, [ctypes.c_void_p]),
     "ff_server_now": (ctypes.c_double, [ctypes.c_void_p]),
     "ff_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ff_frame),
                                         ctypes.POINTER(ff_params), ctypes.POINTER(ff_output),
@@ -534,8 +535,9 @@ class Server:
             pass
 
     @property
-    def lane_pixels(self) -> int:
-        return int(_lib.ff_server_lane_pixels(self.h))
+    def max_pixels(self) -> int:
+        """Largest single frame (pixels) the budget admits."""
+        return int(_lib.ff_server_max_pixels(self.h))
 
     def now(self) -> float:
         return float(_lib.ff_server_now(self.h))

@@ -1,12 +1,19 @@
 // Continuous-batching server for streams of frames from several rigs.
 //
 // Frames are stateless and independent (one fused cloud per time step, nothing carried
-// across frames), so frames of different rigs can share a launch.  The server keeps
+// across frames), so frames of different rigs can share a launch.  The server keeps up to
 // `lanes` resident workspaces, each with its own stream.  A scheduler thread admits arrived
-// frames into the next free lane as one batch (FIFO by arrival, as many as fit the lane's
-// pixel budget and frame limit, equal parameters), launches it with ff_fuse_batch and
-// polls its completion event; the next batch can start on another lane while the previous
-// one still runs.  Latency = completion (observed by the scheduler thread) - arrival.
+// frames into the next free lane as one batch (FIFO by arrival, equal parameters, up to the
+// frame and camera limits) launches it with ff_fuse_batch and polls its completion event;
+// the next batch can start on another lane while the previous one still runs.
+// Latency = completion (observed by the scheduler thread) - arrival.
+//
+// Admission is by device-memory footprint: the lanes' workspaces together stay within the
+// server's budget.  A lane's workspace is sized by the batches it has run (grown when a
+// batch needs more, with the budget's consent); a frame joins a batch only while the
+// batch's workspace fits what the other lanes leave of the budget, so a small frame never
+// reserves room for a large one, and a large frame waits until room is free (idle lanes
+// give theirs back when the head of the queue does not fit anywhere).
 //
 // Ordering with the caller: at submit an event is recorded on the caller's stream, and
 // the lane waits for it before the frame's batch runs, so work the caller queued before
@@ -54,6 +61,9 @@ struct Job {
 
 struct Lane {
     ff_context* ctx = nullptr;
+    uint64_t cap_px = 0;          // workspace limits of ctx (0: no workspace)
+    int32_t cap_cams = 0, cap_frames = 0;
+    uint64_t foot = 0;            // its device bytes
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
@@ -90,7 +100,10 @@ struct DeviceGuard {
 struct ff_server {
     int device = 0;
     ff_server_config cfg{};
-    uint64_t lane_px = 0;
+    uint64_t max_px = 0;          // largest single frame the budget admits (pixels)
+    uint64_t used = 0, peak = 0;  // bytes of the lanes' workspaces now / at most
+    int32_t probe_slot = -1;      // kernel probed in every lane's calls (-1: none)
+    ff_probe probe_gone{};        // probe totals of workspaces already given back
     Clock::time_point t0;
     std::vector<Lane> lanes;
     // shared state (mutex)
@@ -116,25 +129,120 @@ struct ff_server {
     void run();
     bool launch(Lane& L, double t);
     void complete(Lane& L, double t, ff_status st);
+    bool reserve(Lane& L, uint64_t px, int32_t cams, int32_t frames);
+    void release(Lane& L);
 };
 
+// Give the lane a workspace for at least (px, cams, frames) if the budget allows; an idle
+// lane's old workspace is freed first.  Returns false (nothing changed) when it would not
+// fit.
+bool ff_server::reserve(Lane& L, uint64_t px, int32_t cams, int32_t frames) {
+    if (L.ctx && px <= L.cap_px && cams <= L.cap_cams && frames <= L.cap_frames) return true;
+    // grow every limit at least to what is asked, with some headroom for pixels
+    const uint64_t npx = std::max<uint64_t>(px, L.cap_px);
+    const int32_t nc = std::max(cams, L.cap_cams), nf = std::max(frames, L.cap_frames);
+    uint64_t want = npx + npx / 4;
+    if (want >= 0xFFFFFFFEull) want = npx;
+    uint64_t foot = ff_workspace_bytes(want, nc, nf);
+    if (used - L.foot + foot > cfg.hbm_budget_bytes) {
+        want = npx;
+        foot = ff_workspace_bytes(want, nc, nf);
+        if (used - L.foot + foot > cfg.hbm_budget_bytes) return false;
+    }
+    ff_context* keep = L.ctx;
+    if (L.ctx) release(L);
+    ff_context* nctx = nullptr;
+    if (ff_context_create(&nctx, device, want, nc, nf) != FF_OK) return false;
+    if (probe_slot >= 0) (void)ff_probe_enable(nctx, probe_slot);
+    if (keep == nullptr) {
+        // tunings learnt so far by other lanes
+        for (Lane& o : lanes)
+            if (o.ctx) { ff::share_tuning(o.ctx, nctx); break; }
+    }
+    L.ctx = nctx;
+    L.cap_px = want;
+    L.cap_cams = nc;
+    L.cap_frames = nf;
+    L.foot = foot;
+    used += foot;
+    peak = std::max(peak, used);
+    for (Lane& o : lanes)
+        if (o.ctx && &o != &L) ff::share_tuning(o.ctx, L.ctx);
+    return true;
+}
+
+// Free an idle lane's workspace (its stream has no queued work).
+void ff_server::release(Lane& L) {
+    if (!L.ctx) return;
+    (void)hipStreamSynchronize(L.stream);
+    for (Lane& o : lanes)
+        if (o.ctx && &o != &L) ff::share_tuning(L.ctx, o.ctx);
+    if (probe_slot >= 0) {
+        ff_probe p{};
+        if (ff_probe_read(L.ctx, &p) == FF_OK) {
+            probe_gone.launches += p.launches;
+            probe_gone.frames += p.frames;
+            probe_gone.pixels += p.pixels;
+            probe_gone.total_ms += p.total_ms;
+        }
+    }
+    ff_context_destroy(L.ctx);
+    L.ctx = nullptr;
+    used -= L.foot;
+    L.foot = 0;
+    L.cap_px = 0;
+    L.cap_cams = L.cap_frames = 0;
+}
+
 bool ff_server::launch(Lane& L, double t) {
-    // caller holds mu; take arrived frames FIFO while they fit this lane
+    // caller holds mu; take arrived frames FIFO while the batch's workspace fits this lane,
+    // grown as far as the budget the other lanes leave allows
     L.batch.clear();
     uint64_t px = 0, cams = 0;
     const int max_frames = cfg.plain ? 1 : cfg.max_batch_frames;
-    for (auto it = pending.begin(); it != pending.end() && it->first <= t;) {
-        Job& j = it->second;
-        if ((int)L.batch.size() >= max_frames) break;
-        if (!L.batch.empty() && !same_params(j.params, L.batch.front().params)) break;
-        if (px + j.pixels > lane_px || cams + j.cams.size() > (uint64_t)cfg.max_cameras) break;
-        px += j.pixels;
-        cams += j.cams.size();
-        state[j.ticket].phase = kRunning;
-        L.batch.push_back(std::move(j));
-        it = pending.erase(it);
+    const uint64_t room = cfg.hbm_budget_bytes - (used - L.foot);
+    auto first = pending.end();
+    int nb = 0;
+    for (auto it = pending.begin(); it != pending.end() && it->first <= t; ++it) {
+        const Job& j = it->second;
+        if (nb >= max_frames) break;
+        if (nb > 0 && !same_params(j.params, first->second.params)) break;
+        if (cams + j.cams.size() > (uint64_t)cfg.max_cameras) break;
+        const uint64_t npx = px + j.pixels, nc = cams + j.cams.size();
+        const bool fits_now = L.ctx && npx <= L.cap_px && (int32_t)nc <= L.cap_cams &&
+                              nb + 1 <= L.cap_frames;
+        if (!fits_now &&
+            ff_workspace_bytes(std::max<uint64_t>(npx, L.cap_px),
+                               std::max<int32_t>((int32_t)nc, L.cap_cams),
+                               std::max<int32_t>(nb + 1, L.cap_frames)) > room)
+            break;
+        if (nb == 0) first = it;
+        px = npx;
+        cams = nc;
+        ++nb;
     }
-    if (L.batch.empty()) return false;
+    if (nb == 0) return false;
+    if (!reserve(L, px, (int32_t)cams, nb)) {
+        if (used == 0 && L.ctx == nullptr) {
+            // nothing else holds device memory and the workspace still cannot be made:
+            // the head frame cannot run at all
+            auto it = pending.begin();
+            L.batch.push_back(std::move(it->second));
+            pending.erase(it);
+            state[L.batch.back().ticket].phase = kRunning;
+            L.synced = true;
+            L.launch_status = FF_ERR_OOM;
+            L.busy = true;
+            return true;
+        }
+        return false;
+    }
+    for (int k = 0; k < nb; ++k) {
+        auto it = pending.begin();
+        state[it->second.ticket].phase = kRunning;
+        L.batch.push_back(std::move(it->second));
+        pending.erase(it);
+    }
     std::vector<ff_frame> frames(L.batch.size());
     std::vector<ff_output> outs(L.batch.size());
     ff_status st = FF_OK;
@@ -233,11 +341,24 @@ void ff_server::run() {
         if (progressed) cv_done.notify_all();
         // 2. admissions into free lanes
         const double t = now();
+        bool launched = false, idle_free = false;
         for (Lane& L : lanes) {
             if (L.busy) continue;
             if (pending.empty() || pending.begin()->first > t) break;
-            if (launch(L, t)) progressed = true;
+            if (launch(L, t)) progressed = launched = true;
         }
+        if (!launched && !pending.empty() && pending.begin()->first <= t) {
+            // the head of the queue fits no free lane: idle lanes give their workspaces
+            // back (largest first), so that it can be admitted
+            Lane* big = nullptr;
+            for (Lane& L : lanes)
+                if (!L.busy && L.ctx && (!big || L.foot > big->foot)) big = &L;
+            if (big) {
+                release(*big);
+                idle_free = true;
+            }
+        }
+        if (idle_free) continue;
         if (stop && pending.empty() && std::none_of(lanes.begin(), lanes.end(),
                                                     [](const Lane& L) { return L.busy; }))
             break;
@@ -288,26 +409,24 @@ ff_status ff_server_create(ff_server** out, int device, const ff_server_config* 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return FF_ERR_INVALID_ARG;
-    // largest lane (pixels) whose workspace fits budget / lanes
-    const uint64_t per_lane = c.hbm_budget_bytes / (uint64_t)c.lanes;
+    // largest single frame (pixels, at the camera limit) whose workspace fits the budget
     uint64_t lo = 0, hi = 0xFFFFFFFEull;
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo + 1) / 2;
-        if (ff_workspace_bytes(mid, c.max_cameras, c.max_batch_frames) <= per_lane) lo = mid;
+        if (ff_workspace_bytes(mid, c.max_cameras, 1) <= c.hbm_budget_bytes) lo = mid;
         else hi = mid - 1;
     }
     if (lo < 4096) return FF_ERR_OOM;
     ff_server* s = new ff_server();
     s->device = device;
     s->cfg = c;
-    s->lane_px = lo;
+    s->max_px = lo;
     s->t0 = Clock::now();
     DeviceGuard g(device);
     s->lanes.resize(c.lanes);
     ff_status st = FF_OK;
     for (Lane& L : s->lanes) {
-        if ((st = ff_context_create(&L.ctx, device, lo, c.max_cameras, c.max_batch_frames)) != FF_OK)
-            break;
+        // workspaces are made when a lane first takes a batch (sized by it)
         if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
             st = FF_ERR_HIP;
@@ -343,7 +462,7 @@ void ff_server_destroy(ff_server* s) {
     delete s;
 }
 
-uint64_t ff_server_lane_pixels(const ff_server* s) { return s ? s->lane_px : 0; }
+uint64_t ff_server_max_pixels(const ff_server* s) { return s ? s->max_px : 0; }
 
 double ff_server_now(const ff_server* s) { return s ? s->now() : 0.0; }
 
@@ -362,7 +481,10 @@ ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,
     j.out = *out;
     j.pixels = 0;
     for (const ff_camera& c : j.cams) j.pixels += (uint64_t)c.width * (uint64_t)c.height;
-    if (j.pixels > s->lane_px || j.cams.size() > (size_t)s->cfg.max_cameras) return FF_ERR_OOM;
+    // a frame whose own workspace exceeds the whole budget can never be admitted
+    if (j.cams.size() > (size_t)s->cfg.max_cameras ||
+        ff_workspace_bytes(j.pixels, (int32_t)j.cams.size(), 1) > s->cfg.hbm_budget_bytes)
+        return FF_ERR_OOM;
     DeviceGuard g(s->device);
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -444,6 +566,8 @@ ff_status ff_server_stats(const ff_server* cs, ff_stats* st) {
     st->first_arrival_s = s->first_arrival;
     st->last_done_s = s->last_done;
     st->mean_batch_frames = s->batches ? (double)s->batch_frames / (double)s->batches : 0.0;
+    st->hbm_used_bytes = s->used;
+    st->hbm_peak_bytes = s->peak;
     if (!s->lat_ms.empty()) {
         std::vector<double> v = s->lat_ms;
         std::sort(v.begin(), v.end());
@@ -474,10 +598,13 @@ ff_status ff_server_reset_stats(ff_server* s) {
 }
 
 ff_status ff_server_probe_enable(ff_server* s, int32_t slot) {
-    if (!s) return FF_ERR_INVALID_ARG;
+    if (!s || slot < -1 || slot >= FF_TRACE_SLOTS) return FF_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);    // the scheduler launches under this lock
     ff_status st = FF_OK;
+    s->probe_slot = slot;
+    s->probe_gone = ff_probe{};
     for (Lane& L : s->lanes) {
+        if (!L.ctx) continue;
         const ff_status e = ff_probe_enable(L.ctx, slot);
         if (e != FF_OK) st = e;
     }
@@ -488,9 +615,14 @@ ff_status ff_server_probe_read(ff_server* s, ff_probe* out) {
     if (!s || !out) return FF_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     std::memset(out, 0, sizeof(*out));
-    out->slot = -1;
+    out->slot = s->probe_slot;
+    out->launches = s->probe_gone.launches;
+    out->frames = s->probe_gone.frames;
+    out->pixels = s->probe_gone.pixels;
+    out->total_ms = s->probe_gone.total_ms;
     ff_status st = FF_OK;
     for (Lane& L : s->lanes) {
+        if (!L.ctx) continue;
         ff_probe p{};
         const ff_status e = ff_probe_read(L.ctx, &p);
         if (e != FF_OK) st = e;

@@ -204,7 +204,7 @@ def test_server_admission_by_footprint(ff):
     f = cached_frame("c2")                                     # 1.2 Mpx
     d = ff.to_device(f)
     srv = ff.Server(hbm_budget_bytes=24 << 20, lanes=1, max_batch_frames=2)
-    assert srv.lane_pixels < f.pixels
+    assert srv.max_pixels < f.pixels
     with pytest.raises(ff.FuseFlowError) as e:
         srv.submit(0, d, ff.Output(16))
     assert e.value.status == ff.FF_ERR_OOM
@@ -217,6 +217,45 @@ def test_server_admission_by_footprint(ff):
         srv.poll(t)
     assert e.value.status == ff.FF_ERR_NOT_FOUND
     assert out.result()["count"] == len(O.fuse_frame(small)["keys"])
+    srv.close()
+
+
+def test_server_admits_by_each_frames_footprint(ff):
+    """The budget holds one large frame's workspace or several small ones, not both: small
+    frames run side by side on the lanes, a large frame waits until they are done (idle
+    lanes give their workspaces back), the device bytes of all workspaces never exceed the
+    budget, and every result equals ff_fuse."""
+    print("[case] footprint admission", flush=True)
+    big, small = cached_frame("c2"), cached_frame("c1")
+    db, ds = ff.to_device(big), ff.to_device(small)
+    wb = int(ff.lib().ff_workspace_bytes(big.pixels, len(big.cams), 1))
+    ws = int(ff.lib().ff_workspace_bytes(small.pixels, len(small.cams), 1))
+    budget = int(wb * 1.3)                 # the large frame with headroom, or 2+ small ones
+    assert budget < wb + 2 * ws and budget > 2 * ws
+    ref_b, ref_s = _alone(ff, db), _alone(ff, ds)
+    srv = ff.Server(hbm_budget_bytes=budget, lanes=3, max_batch_frames=1)
+    outs = []
+    for rep in range(3):
+        for name, d, P in (("s", ds, small.pixels), ("s", ds, small.pixels), ("b", db, big.pixels)):
+            o = ff.Output(P, rgb=True)
+            srv.submit(0, d, o)
+            outs.append((name, o))
+    srv.drain()
+    st = srv.stats()
+    assert st["frames"] == 9 and 0 < st["hbm_peak_bytes"] <= budget, st
+    for name, o in outs:
+        g, r = o.result(), (ref_s if name == "s" else ref_b)
+        for k in KEYS:
+            assert np.array_equal(g[k], r[k]), (name, k)
+    # a frame larger than the whole budget is refused; the server keeps serving
+    tiny = ff.Server(hbm_budget_bytes=ws + ws // 2, lanes=2, max_batch_frames=1)
+    with pytest.raises(ff.FuseFlowError) as e:
+        tiny.submit(0, db, ff.Output(big.pixels))
+    assert e.value.status == ff.FF_ERR_OOM
+    o = ff.Output(small.pixels, rgb=True)
+    tiny.wait(tiny.submit(0, ds, o))
+    assert np.array_equal(o.result()["keys"], ref_s["keys"])
+    tiny.close()
     srv.close()
 
 
