@@ -20,6 +20,11 @@ After them, a timed region of the same steps in the serving batch size, batched 
 after another on the caller's stream, times that kernel alone with events around it
 (roofline), and the CPU oracle runs on a bounded sample (cpu_baseline); the same frames go
 through the server in the timed configuration and are checked against the oracle's output.
+Beside the headline: the two workloads whose inputs exceed the last-level cache (the
+30-frame 16-camera sequence in batched calls; rigs of 2/6/12/32 cameras served at saturation
+and as a 30 Hz Poisson stream for --c5-seconds, p50/p99 against the plain loop), each with
+its fraction of the HBM roofline; a 1/2/4/8-camera sweep at 1280x720; and the oracle on the
+two small configurations in full and on one 16-camera frame, each checked against the GPU.
 --copy-calibration MiB first runs a plain elementwise copy (read N, write N bytes) so that
 hardware byte counters of the same profiled run can be scaled.
 Prints ONE JSON line.
@@ -125,14 +130,8 @@ def serving_parity(ff, torch, np, O, frames, devs, oracle_out, P, params, args):
     srv.close()
     ok, worst_xyz, worst_w = True, 0.0, 0.0
     for o, g in zip(oracle_out, (x.result() for x in outs)):
-        same = (g["status"] == 0 and g["count"] == len(o["keys"]) and
-                all(np.array_equal(g[k], o[k]) for k in ("keys", "n_members", "reps")))
-        scale = np.maximum(np.abs(o["xyz"]).max(axis=1), 1.0)
-        ex = float((np.abs(g["xyz"].astype(np.float64) - o["xyz"]).max(axis=1) / scale).max())
-        ew = float((np.abs(g["weight"].astype(np.float64) - o["weight"]) /
-                    np.maximum(o["weight"], 1e-6)).max())
-        rgb_ok = int(np.abs(g["rgb"].astype(int) - o["rgb"].astype(int)).max()) <= 1
-        ok = ok and same and ex <= 1e-5 and ew <= 1e-5 and rgb_ok
+        good, ex, ew = compare_to_oracle(np, g, o)
+        ok = ok and good
         worst_xyz, worst_w = max(worst_xyz, ex), max(worst_w, ew)
     return {"frames": len(devs), "ok": bool(ok), "max_rel_xyz_err": worst_xyz,
             "max_rel_weight_err": worst_w}
@@ -140,59 +139,110 @@ def serving_parity(ff, torch, np, O, frames, devs, oracle_out, P, params, args):
 
 MALL_BYTES = 256 << 20
 WARM_SECONDS = 0.5      # untimed work before each larger-workload measurement
+C4_FRAMES = 30          # length of the 16-camera dynamic sequence
 
 
-def run_regimes(ff, torch, params, stream, args):
+def render_inputs(name, frame, rig=0):
+    """The inputs of one synthetic frame (cameras, depth, confidence, colour) in a form that
+    crosses a process pool cheaply (no ground-truth layers)."""
+    import types
+    from synth import make_config
+    f = make_config(name, frame=frame, rig=rig)
+    return types.SimpleNamespace(cams=f.cams, depth=f.depth, conf=f.conf, rgb=f.rgb)
+
+
+def compare_to_oracle(np, g, o):
+    """count, keys, member counts and representatives bit for bit; fused coordinates and
+    weights within 1e-5 (relative; floors 1 m and 1e-6); colours within 1."""
+    same = (g["status"] == 0 and g["count"] == len(o["keys"]) and
+            all(np.array_equal(g[k], o[k]) for k in ("keys", "n_members", "reps")))
+    scale = np.maximum(np.abs(o["xyz"]).max(axis=1), 1.0) if len(o["keys"]) else 1.0
+    ex = float((np.abs(g["xyz"].astype(np.float64) - o["xyz"]).max(axis=1) / scale).max()) \
+        if len(o["keys"]) else 0.0
+    ew = float((np.abs(g["weight"].astype(np.float64) - o["weight"]) /
+                np.maximum(o["weight"], 1e-6)).max()) if len(o["keys"]) else 0.0
+    rgb_ok = (g.get("rgb") is None or o.get("rgb") is None or not len(o["keys"]) or
+              int(np.abs(g["rgb"].astype(int) - o["rgb"].astype(int)).max()) <= 1)
+    return same and ex <= 1e-5 and ew <= 1e-5 and rgb_ok, ex, ew
+
+
+def frame_sizes(ff, dev, params, stream):
+    """P, M, S, R of one frame (one ff_fuse call of its own), for the algorithmic bytes."""
+    P = sum(int(c.width) * int(c.height) for c in dev["cams"])
+    ctx = ff.Context(max_pixels=P, max_cameras=len(dev["cams"]))
+    o = ff.Output(P)
+    ctx.fuse(dev["cams"], dev["depth"], dev["conf"], None, params=params, out=o, stream=stream)
+    info = o.result()["info"]
+    ctx.close()
+    return dict(P=P, M=int(info[0]), S=int(info[1]), R=int(info[2]))
+
+
+def run_regimes(ff, torch, params, stream, args, c4_host):
     """Throughput of the two larger workloads, whose inputs per call or step exceed the
     256 MB last-level cache (one headline frame's 81 MB of inputs fits it); each is the
     median of three timed runs after half a second of untimed work:
-      * 16 cameras at mixed resolutions (6 x 640x480, 6 x 1280x720, 4 x 1920x1080), two
-        frames of the moving-sphere sequence per batched call (ff_fuse_batch), with the tile
-        and digit sizes the autotuner picks for that batch;
+      * 16 cameras at mixed resolutions (6 x 640x480, 6 x 1280x720, 4 x 1920x1080): the
+        30 frames of the moving-sphere sequence, two frames per batched call
+        (ff_fuse_batch, replayed from a hipGraph), with the tile and digit sizes the
+        autotuner picks for that batch shape;
       * rigs of 2, 6, 12 and 32 cameras (resolutions drawn from 640x480, 1280x720,
         1920x1080) through the continuous-batching server at saturation and through the
-        plain loop."""
+        plain loop, then the Poisson stream of those rigs at 30 Hz."""
     from synth import make_config
     res = {}
     t0 = time.time()
-    seq = [ff.to_device(make_config("c4", frame=i)) for i in range(2)]
+    seq = [ff.to_device(f) for f in c4_host]
+    nseq = len(seq)
     P16 = sum(int(c.width) * int(c.height) for c in seq[0]["cams"])
-    in_bytes = sum(t.numel() * t.element_size() for d in seq
+    in_bytes = sum(t.numel() * t.element_size() for d in seq[:2]
                    for t in d["depth"] + d["conf"] + d["rgb"])
     ctx = ff.Context(max_pixels=2 * P16, max_cameras=32, max_frames=2)
     outs = [ff.Output(P16, rgb=True) for _ in range(2)]
-    tuned = ctx.autotune(seq, params=params, outs=outs, stream=stream)
+    tuned = ctx.autotune(seq[:2], params=params, outs=outs, stream=stream)
+    pairs = [seq[i:i + 2] for i in range(0, nseq - 1, 2)]
     # the GPU idled while the frames were rendered: keep it saturated for a while (clocks
     # ramp up over tens of milliseconds) before timing, then take the median of three runs
     t_end = time.perf_counter() + WARM_SECONDS
     while time.perf_counter() < t_end:
-        for _ in range(8):
-            ctx.fuse_batch(seq, params=params, outs=outs, stream=stream)
+        for pr in pairs[:8]:
+            ctx.fuse_batch(pr, params=params, outs=outs, stream=stream)
         torch.cuda.synchronize()
-    calls = max(4, args.steps // 2)
+    reps = max(1, args.steps // (2 * len(pairs)))     # passes over the sequence per run
 
     def timed():
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(calls):
-            ctx.fuse_batch(seq, params=params, outs=outs, stream=stream)
+        for _ in range(reps):
+            for pr in pairs:
+                ctx.fuse_batch(pr, params=params, outs=outs, stream=stream)
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
     runs = sorted(timed() for _ in range(3))
     dt = runs[1]
     ctx.close()
+    K = params.k_views
+    zs = [frame_sizes(ff, d, params, stream) for d in seq[:2 * len(pairs)]]
+    B_pass = sum(frame_alg_bytes(z["P"], z["M"], z["S"], z["R"], K) for z in zs)
+    nfr = reps * 2 * len(pairs)
     res["mixed16_batched"] = {
-        "px_s": 2 * calls * P16 / dt, "ms_per_frame": dt / (2 * calls) * 1e3,
-        "pixels_per_frame": P16, "frames_per_call": 2, "calls": calls, "tuning": tuned,
-        "runs_ms_per_frame": [round(r / (2 * calls) * 1e3, 4) for r in runs],
+        "sequence_frames": 2 * len(pairs), "passes_per_run": reps,
+        "alg_bytes_per_frame": B_pass / len(zs),
+        "frac_hbm": round(reps * B_pass / dt / (HBM_PEAK_GBS * 1e9), 4),
+        "px_s": nfr * P16 / dt, "ms_per_frame": dt / nfr * 1e3,
+        "fused_points_per_s": reps * sum(z["S"] for z in zs) / dt,
+        "pixels_per_frame": P16, "frames_per_call": 2, "tuning": tuned,
+        "runs_ms_per_frame": [round(r / nfr * 1e3, 4) for r in runs],
         "input_mb_per_call": round(in_bytes / 1e6, 1),
         "regime": "HBM: inputs exceed the 256 MB last-level cache" if in_bytes > MALL_BYTES
                   else "inputs fit the 256 MB last-level cache"}
-    del seq
+    del seq, pairs
+    torch.cuda.empty_cache()
 
     rigs = [ff.to_device(make_config("c5", rig=r)) for r in range(4)]
     Pr = [sum(int(c.width) * int(c.height) for c in d["cams"]) for d in rigs]
+    zr = [frame_sizes(ff, d, params, stream) for d in rigs]
+    B_step = sum(frame_alg_bytes(z["P"], z["M"], z["S"], z["R"], K) for z in zr)
     in_bytes = sum(t.numel() * t.element_size() for d in rigs
                    for t in d["depth"] + d["conf"] + d["rgb"])
     routs = [[ff.Output(p, rgb=True) for _ in range(2)] for p in Pr]
@@ -224,13 +274,124 @@ def run_regimes(ff, torch, params, stream, args):
             runs.append((run(srv, steps), srv.stats()["mean_batch_frames"]))
         dt, mbf = sorted(runs)[1]
         row[name] = {"px_s": steps * sum(Pr) / dt, "steps": steps, "mean_batch_frames": mbf,
+                     "frac_hbm": round(steps * B_step / dt / (HBM_PEAK_GBS * 1e9), 4),
                      "runs_px_s": [steps * sum(Pr) / r for r, _ in runs]}
         srv.close()
     row["speedup_serving_vs_plain"] = row["serving"]["px_s"] / row["plain"]["px_s"]
+    row["alg_bytes_per_step"] = B_step
+    # the serving stream itself: Poisson arrivals at 30 Hz per rig (seeds 7000 + rig) for
+    # args.c5_seconds, the same trace through the server and through the plain loop
+    if args.c5_seconds > 0:
+        from synth.scenes import poisson_arrivals
+        trace = sorted((float(a), r) for r in range(4)
+                       for a in poisson_arrivals(30.0, args.c5_seconds, 7000 + r))
+        tr = {"rate_hz_per_rig": 30.0, "seconds": args.c5_seconds, "frames": len(trace),
+              "offered_px_s": sum(Pr[r] for _, r in trace) / args.c5_seconds}
+        for name, kw in (("serving", dict(lanes=args.lanes, max_batch_frames=args.batch)),
+                         ("plain", dict(plain=True))):
+            srv = ff.Server(hbm_budget_bytes=24 << 30, max_pending=1 << 20, **kw)
+            for r, d in enumerate(rigs):                  # workspaces, graphs
+                srv.submit(r, d, routs[r][0], params)
+            srv.drain()
+            srv.reset_stats()
+            lead = srv.now() + 0.2
+            count = [0] * 4
+            for a, r in trace:
+                srv.submit(r, rigs[r], routs[r][count[r] % 2], params, arrival_s=lead + a)
+                count[r] += 1
+            srv.drain()
+            st = srv.stats()
+            tr[name] = dict(p50_ms=round(st["p50_ms"], 4), p99_ms=round(st["p99_ms"], 4),
+                            mean_ms=round(st["mean_ms"], 4), max_ms=round(st["max_ms"], 4),
+                            frames=int(st["frames"]),
+                            mean_batch_frames=round(st["mean_batch_frames"], 3),
+                            hbm_peak_bytes=int(st["hbm_peak_bytes"]))
+            srv.close()
+        row["poisson_30hz"] = tr
+        log(f"rigs 2/6/12/32 at 30 Hz: serving p50 {tr['serving']['p50_ms']:.2f} / p99 "
+            f"{tr['serving']['p99_ms']:.2f} ms; plain p50 {tr['plain']['p50_ms']:.2f} / p99 "
+            f"{tr['plain']['p99_ms']:.2f} ms")
     res["rigs_2_6_12_32_served"] = row
     log(f"larger workloads in {time.time() - t0:.1f} s: 16 mixed cameras "
         f"{res['mixed16_batched']['px_s'] / 1e9:.2f} Gpx/s; rigs 2/6/12/32 serving "
         f"{row['serving']['px_s'] / 1e9:.2f} Gpx/s, plain {row['plain']['px_s'] / 1e9:.2f}")
+    return res
+
+
+def camera_sweep(ff, torch, dev, params, stream, args):
+    """Cost against camera count: the first 1, 2, 4 and 8 cameras of a headline frame
+    (1280x720 each) through ff_fuse, calls back to back on one stream (median of three
+    timed runs), plus the summed kernel time of one call from the per-kernel trace, and the
+    least-squares line of time per frame against the camera count."""
+    import numpy as np
+    rows = {}
+    calls = max(10, args.steps // 2)
+    for n in (1, 2, 4, 8):
+        sub = {k: v[:n] for k, v in dev.items()}
+        P = sum(int(c.width) * int(c.height) for c in sub["cams"])
+        ctx = ff.Context(max_pixels=P, max_cameras=n)
+        out = ff.Output(P, rgb=True)
+
+        def call():
+            ctx.fuse(sub["cams"], sub["depth"], sub["conf"], sub["rgb"], params=params,
+                     out=out, stream=stream)
+
+        for _ in range(5):
+            call()
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            t = time.perf_counter()
+            for _ in range(calls):
+                call()
+            torch.cuda.synchronize()
+            runs.append((time.perf_counter() - t) / calls)
+        ctx.trace(True)
+        for _ in range(5):
+            call()
+        tr = ctx.trace_read()
+        ctx.trace(False)
+        info = out.result()["info"]
+        ctx.close()
+        dt = sorted(runs)[1]
+        rows[n] = {"pixels": P, "ms_per_frame": round(dt * 1e3, 4), "px_s": P / dt,
+                   "kernel_ms_per_frame": round(sum(v["total_ms"] for v in tr["kernels"].values())
+                                                / max(1, tr["calls"]), 4),
+                   "M": int(info[0]), "S": int(info[1])}
+    ns = np.array(sorted(rows), dtype=np.float64)
+    ts = np.array([rows[int(n)]["ms_per_frame"] for n in ns])
+    slope, icpt = np.polyfit(ns, ts, 1)
+    fit = slope * ns + icpt
+    log("cameras 1/2/4/8: " + ", ".join(f"{rows[int(n)]['ms_per_frame']:.3f}" for n in ns)
+        + f" ms per frame; {slope:.4f} ms per camera + {icpt:.4f} ms")
+    return {"frames": {str(n): v for n, v in rows.items()}, "calls_per_run": calls,
+            "fit_ms_per_camera": round(float(slope), 5), "fit_intercept_ms": round(float(icpt), 5),
+            "fit_max_rel_residual": round(float(np.max(np.abs(ts - fit) / ts)), 4)}
+
+
+def oracle_configs(ff, np, O, params, stream, c4_frame):
+    """The oracle on the two small configurations in full (2 x 320x240; 4 x 640x480) and
+    on one 16-camera frame (15.7 Mpx), each checked against ff_fuse on the same frame."""
+    from synth import make_config
+    res = {}
+    for name, host in (("c1_2x320x240", make_config("c1")), ("c2_4x640x480", make_config("c2")),
+                       ("c4_16_mixed_frame0", c4_frame)):
+        P = sum(int(c.width) * int(c.height) for c in host.cams)
+        c0, w0 = time.process_time(), time.perf_counter()
+        o = O.fuse_frame(host)
+        wall = time.perf_counter() - w0
+        cpu_t = time.process_time() - c0
+        dev = ff.to_device(host)
+        ctx = ff.Context(max_pixels=P, max_cameras=len(host.cams))
+        out = ff.Output(P, rgb=True)
+        ctx.fuse(dev["cams"], dev["depth"], dev["conf"], dev["rgb"], params=params, out=out,
+                 stream=stream)
+        good, ex, ew = compare_to_oracle(np, out.result(), o)
+        ctx.close()
+        res[name] = {"pixels": P, "seconds": round(wall, 3), "px_s": P / wall,
+                     "cores": max(1, round(cpu_t / wall)), "cells": len(o["keys"]),
+                     "parity_ok": bool(good), "max_rel_xyz_err": ex, "max_rel_weight_err": ew}
+        log(f"oracle {name}: {wall:.2f} s, parity {'ok' if good else 'FAILED'}")
     return res
 
 
@@ -248,6 +409,8 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="run a plain copy kernel of this size first (counter scaling)")
+    ap.add_argument("--c5-seconds", type=float, default=10.0,
+                    help="length of the 30 Hz Poisson stream of the 2/6/12/32-camera rigs")
     ap.add_argument("--no-regimes", action="store_true",
                     help="skip the two larger workloads (16 mixed cameras; 2/6/12/32 rigs)")
     args = ap.parse_args()
@@ -257,6 +420,17 @@ def main():
               "are independent and would shard across GPUs by frame or rig, with no "
               "communication)", file=sys.stderr)
         sys.exit(2)
+
+    # the 16-camera sequence renders in worker processes (started before anything touches
+    # the GPU) while this one renders the headline frames
+    c4_jobs, pool = [], None
+    if not args.no_regimes or not args.no_cpu_baseline:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        pool = cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1),
+                                      mp_context=mp.get_context("spawn"))
+        n4 = C4_FRAMES if not args.no_regimes else 1
+        c4_jobs = [pool.submit(render_inputs, "c4", i) for i in range(n4)]
 
     import numpy as np
     import torch
@@ -488,7 +662,13 @@ def main():
     log(f"copy {copy_gbs:.0f} GB/s")
 
     # ------------------------------------------------------------------ larger workloads
-    regimes = None if args.no_regimes else run_regimes(ff, torch, params, stream, args)
+    c4_host = [f.result() for f in c4_jobs]
+    if pool is not None:
+        pool.shutdown()
+    regimes = None if args.no_regimes else run_regimes(ff, torch, params, stream, args, c4_host)
+
+    # ------------------------------------------------------------------ camera sweep
+    sweep = camera_sweep(ff, torch, devs[(0, 0)], params, stream, args)
 
     # ------------------------------------------------------------------ CPU oracle
     cpu = None
@@ -509,6 +689,7 @@ def main():
         cpu["parity"] = serving_parity(ff, torch, np, O, [frames[k] for k in sample],
                                        [devs[k] for k in sample], oracle_out, P, params, args)
         log(f"parity of the served frames against the oracle: {cpu['parity']}")
+        cpu["other_configs"] = oracle_configs(ff, np, O, params, stream, c4_host[0])
 
     line = {
         "metric": METRIC, "value": px_srv, "unit": "px/s", "n_gpus": 1, "steps": args.steps,
@@ -537,6 +718,7 @@ def main():
         "roofline": roofline,
         "frame_roofline": frame_roofline,
         "regimes": regimes,
+        "camera_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
