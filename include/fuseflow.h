@@ -384,6 +384,11 @@ ff_status ff_server_drain(ff_server* s);
 ff_status ff_server_stats(const ff_server* s, ff_stats* st);
 /* Forget completed frames' latencies (stats restart from zero). */
 ff_status ff_server_reset_stats(ff_server* s);
+/* The latency of every frame completed since the last reset, in completion order, with
+ * its rig: the first min(cap, *n) go to rig_ids and latency_ms (host arrays; either may be
+ * NULL), *n is set to how many there are.  For per-rig percentiles beside ff_stats. */
+ff_status ff_server_latencies(const ff_server* s, uint64_t cap, int32_t* rig_ids,
+                              double* latency_ms, uint64_t* n);
 /* The probe on every lane (see ff_probe_enable); read sums the lanes.  Both wait for the
  * lanes' recorded launches to finish. */
 ff_status ff_server_probe_enable(ff_server* s, int32_t slot);

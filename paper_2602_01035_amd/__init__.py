@@ -164,6 +164,10 @@ EXPORTS = {
     "ff_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
     "ff_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_stats)]),
     "ff_server_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
+    "ff_server_latencies": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
     "ff_server_probe_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ff_server_probe_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_probe)]),
 }
@@ -588,6 +592,24 @@ class Server:
 
     def reset_stats(self):
         _check(_lib.ff_server_reset_stats(self.h), "ff_server_reset_stats")
+
+    def latencies(self):
+        """(rig ids, latencies in ms) of the frames completed since the last reset, in
+        completion order (NumPy arrays)."""
+        import numpy as np
+        n = ctypes.c_uint64(0)
+        _check(_lib.ff_server_latencies(self.h, 0, None, None, ctypes.byref(n)),
+               "ff_server_latencies")
+        while True:
+            cap = n.value
+            rigs = np.zeros(cap, np.int32)
+            lat = np.zeros(cap, np.float64)
+            _check(_lib.ff_server_latencies(
+                self.h, cap, rigs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)),
+                "ff_server_latencies")
+            if n.value <= cap:
+                return rigs[:n.value], lat[:n.value]
 
     def probe(self, slot: int):
         """Time trace slot `slot` in every later batch on every lane (-1: off)."""

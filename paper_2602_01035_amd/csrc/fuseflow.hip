@@ -836,24 +836,29 @@ ff_status dispatch_plain(ff_context* c, const Ctx& C, const Plan& plan, hipStrea
 ff_status run_graph(ff_context* c, const Ctx& C, const Plan& plan, const std::string& key,
                     hipStream_t s) {
     auto it = c->graphs.find(key);
-    if (it == c->graphs.end()) {
-        if (c->graphs.size() >= 64) {
-            FF_HIP(hipStreamSynchronize(s));
-            drop_graphs(c);
-        }
-        hipGraph_t g = nullptr;
-        FF_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        ff_status st = dispatch_plain(c, C, plan, c->cap_stream);
-        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-        if (st != FF_OK) { if (g) (void)hipGraphDestroy(g); return st; }
-        FF_HIP(e);
-        hipGraphExec_t ex = nullptr;
-        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        FF_HIP(e);
-        it = c->graphs.emplace(key, ex).first;
+    if (it != c->graphs.end()) {
+        FF_HIP(hipGraphLaunch(it->second, s));
+        return FF_OK;
     }
-    FF_HIP(hipGraphLaunch(it->second, s));
+    // the first batch of a shape: its kernels go to the stream at once, and the graph for
+    // the next ones is captured (on a stream of its own) and instantiated while they run
+    if (c->graphs.size() >= 64) {
+        FF_HIP(hipStreamSynchronize(s));
+        drop_graphs(c);
+    }
+    ff_status st = dispatch_plain(c, C, plan, s);
+    if (st != FF_OK) return st;
+    hipGraph_t g = nullptr;
+    FF_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    st = dispatch_plain(c, C, plan, c->cap_stream);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != FF_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    FF_HIP(e);
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FF_HIP(e);
+    c->graphs.emplace(key, ex);
     return FF_OK;
 }
 

@@ -68,6 +68,7 @@ struct Lane {
     hipEvent_t done = nullptr;
     bool busy = false;
     bool synced = false;          // the lane's work is known complete (no event to query)
+    int32_t last_rig = -1;        // rig of the first frame of its last batch
     ff_status launch_status = FF_OK;
     std::vector<Job> batch;
 };
@@ -118,7 +119,8 @@ struct ff_server {
     ff_status drain_status = FF_OK;       // first failure since the last drain
     bool stop = false;
     // stats (mutex)
-    std::vector<double> lat_ms;
+    std::vector<double> lat_ms;        // completed frames, in completion order
+    std::vector<int32_t> lat_rig;      // their rigs
     uint64_t frames = 0, pixels = 0, batches = 0, batch_frames = 0;
     double first_arrival = -1.0, last_done = 0.0;
     std::thread worker;
@@ -128,6 +130,7 @@ struct ff_server {
     }
     void run();
     bool launch(Lane& L, double t);
+    std::vector<Lane*> lane_order(const Job& head);
     void complete(Lane& L, double t, ff_status st);
     bool reserve(Lane& L, uint64_t px, int32_t cams, int32_t frames);
     void release(Lane& L);
@@ -192,6 +195,31 @@ void ff_server::release(Lane& L) {
     L.foot = 0;
     L.cap_px = 0;
     L.cap_cams = L.cap_frames = 0;
+    L.last_rig = -1;
+}
+
+// Free lanes in the order the head frame should try them: lanes whose workspace holds it
+// as it is (the one that last ran its rig first: its graphs for the rig's shape are
+// cached; then the smallest), then lanes without a workspace, then the others, largest
+// first (growing a lane frees and re-creates its workspace and captures new graphs).
+std::vector<Lane*> ff_server::lane_order(const Job& head) {
+    std::vector<Lane*> fit, empty, grow;
+    for (Lane& L : lanes) {
+        if (L.busy) continue;
+        if (!L.ctx) empty.push_back(&L);
+        else if (head.pixels <= L.cap_px && (int32_t)head.cams.size() <= L.cap_cams) fit.push_back(&L);
+        else grow.push_back(&L);
+    }
+    std::stable_sort(fit.begin(), fit.end(), [&](const Lane* a, const Lane* b) {
+        const bool ra = a->last_rig == head.rig, rb = b->last_rig == head.rig;
+        if (ra != rb) return ra;
+        return a->foot < b->foot;
+    });
+    std::stable_sort(grow.begin(), grow.end(),
+                     [](const Lane* a, const Lane* b) { return a->foot > b->foot; });
+    fit.insert(fit.end(), empty.begin(), empty.end());
+    fit.insert(fit.end(), grow.begin(), grow.end());
+    return fit;
 }
 
 bool ff_server::launch(Lane& L, double t) {
@@ -243,6 +271,7 @@ bool ff_server::launch(Lane& L, double t) {
         L.batch.push_back(std::move(it->second));
         pending.erase(it);
     }
+    L.last_rig = L.batch.front().rig;
     std::vector<ff_frame> frames(L.batch.size());
     std::vector<ff_output> outs(L.batch.size());
     ff_status st = FF_OK;
@@ -302,6 +331,7 @@ void ff_server::complete(Lane& L, double t, ff_status st) {
         if (st == FF_OK) {
             if (first_arrival < 0 || j.arrival < first_arrival) first_arrival = j.arrival;
             lat_ms.push_back((t - j.arrival) * 1e3);
+            lat_rig.push_back(j.rig);
             ++frames;
             pixels += j.pixels;
         }
@@ -339,13 +369,15 @@ void ff_server::run() {
             }
         }
         if (progressed) cv_done.notify_all();
-        // 2. admissions into free lanes
+        // 2. admissions into free lanes, in the order of preference for the head frame
         const double t = now();
         bool launched = false, idle_free = false;
-        for (Lane& L : lanes) {
-            if (L.busy) continue;
-            if (pending.empty() || pending.begin()->first > t) break;
-            if (launch(L, t)) progressed = launched = true;
+        while (!pending.empty() && pending.begin()->first <= t) {
+            bool any = false;
+            for (Lane* L : lane_order(pending.begin()->second))
+                if (launch(*L, t)) { any = true; break; }
+            if (!any) break;
+            progressed = launched = true;
         }
         if (!launched && !pending.empty() && pending.begin()->first <= t) {
             // the head of the queue fits no free lane: idle lanes give their workspaces
@@ -587,10 +619,25 @@ ff_status ff_server_stats(const ff_server* cs, ff_stats* st) {
     return FF_OK;
 }
 
+ff_status ff_server_latencies(const ff_server* cs, uint64_t cap, int32_t* rig_ids,
+                              double* latency_ms, uint64_t* n) {
+    if (!cs || !n) return FF_ERR_INVALID_ARG;
+    ff_server* s = const_cast<ff_server*>(cs);
+    std::lock_guard<std::mutex> lk(s->mu);
+    *n = s->lat_ms.size();
+    const size_t k = (size_t)std::min<uint64_t>(cap, s->lat_ms.size());
+    for (size_t i = 0; i < k; ++i) {
+        if (rig_ids) rig_ids[i] = s->lat_rig[i];
+        if (latency_ms) latency_ms[i] = s->lat_ms[i];
+    }
+    return FF_OK;
+}
+
 ff_status ff_server_reset_stats(ff_server* s) {
     if (!s) return FF_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     s->lat_ms.clear();
+    s->lat_rig.clear();
     s->frames = s->pixels = s->batches = s->batch_frames = 0;
     s->first_arrival = -1.0;
     s->last_done = 0.0;

@@ -193,6 +193,15 @@ def test_server_results_same_alone_and_in_mix(ff, plain):
     assert st["frames"] == len(outs) and st["p99_ms"] >= st["p50_ms"] > 0
     if plain:
         assert st["mean_batch_frames"] == 1.0
+    # the per-frame samples: one per completed frame with its rig, agreeing with the stats
+    rigs, lat = srv.latencies()
+    assert len(lat) == len(outs)
+    assert sorted(np.bincount(rigs).tolist()) == sorted(
+        np.bincount([i % 3 for i, _ in outs]).tolist())
+    assert lat.max() == pytest.approx(st["max_ms"]) and lat.mean() == pytest.approx(st["mean_ms"])
+    assert np.sort(lat)[int(np.ceil(0.5 * len(lat))) - 1] == pytest.approx(st["p50_ms"])
+    srv.reset_stats()
+    assert len(srv.latencies()[1]) == 0
     srv.close()
 
 
