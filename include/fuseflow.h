@@ -354,6 +354,15 @@ void ff_server_destroy(ff_server* s);
 /* Largest single frame (pixels, with the configured camera limit) the budget admits. */
 uint64_t ff_server_max_pixels(const ff_server* s);
 
+/* Size every idle lane's workspace now for a batch of `frames` frames with `pixels` pixels
+ * and `cameras` cameras in all (lanes already that large are left as they are), so that
+ * streams of such frames meet no workspace creation later.  Lanes are sized in order while
+ * the budget allows: FF_ERR_OOM if it ran out before the last lane (the lanes sized so far
+ * keep their workspaces), FF_ERR_BUSY if a lane was running a batch (call it before
+ * submitting or after a drain), FF_ERR_INVALID_ARG for sizes beyond the configured camera
+ * or batch limits. */
+ff_status ff_server_reserve(ff_server* s, uint64_t pixels, int32_t cameras, int32_t frames);
+
 /* Seconds on the server clock (steady clock, zero at creation). */
 double ff_server_now(const ff_server* s);
 

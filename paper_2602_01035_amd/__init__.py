@@ -164,6 +164,8 @@ EXPORTS = {
     "ff_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
     "ff_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ff_stats)]),
     "ff_server_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
+    "ff_server_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                         ctypes.c_int32]),
     "ff_server_latencies": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double),
@@ -592,6 +594,11 @@ class Server:
 
     def reset_stats(self):
         _check(_lib.ff_server_reset_stats(self.h), "ff_server_reset_stats")
+
+    def reserve(self, pixels: int, cameras: int, frames: int = 1):
+        """Size every idle lane's workspace now for such a batch (ff_server_reserve)."""
+        _check(_lib.ff_server_reserve(self.h, int(pixels), int(cameras), int(frames)),
+               "ff_server_reserve")
 
     def latencies(self):
         """(rig ids, latencies in ms) of the frames completed since the last reset, in

@@ -496,6 +496,23 @@ void ff_server_destroy(ff_server* s) {
 
 uint64_t ff_server_max_pixels(const ff_server* s) { return s ? s->max_px : 0; }
 
+ff_status ff_server_reserve(ff_server* s, uint64_t pixels, int32_t cameras, int32_t frames) {
+    if (!s || pixels == 0 || cameras < 1 || frames < 1 || cameras > s->cfg.max_cameras ||
+        frames > (s->cfg.plain ? 1 : s->cfg.max_batch_frames))
+        return FF_ERR_INVALID_ARG;
+    DeviceGuard g(s->device);
+    std::lock_guard<std::mutex> lk(s->mu);
+    ff_status st = FF_OK;
+    for (Lane& L : s->lanes) {
+        if (L.busy) {
+            st = FF_ERR_BUSY;
+            continue;
+        }
+        if (!s->reserve(L, pixels, cameras, frames) && st == FF_OK) st = FF_ERR_OOM;
+    }
+    return st;
+}
+
 double ff_server_now(const ff_server* s) { return s ? s->now() : 0.0; }
 
 ff_status ff_server_submit(ff_server* s, int32_t rig_id, const ff_frame* frame,

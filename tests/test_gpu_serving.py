@@ -229,6 +229,52 @@ def test_server_admission_by_footprint(ff):
     srv.close()
 
 
+def test_server_reserve_sizes_idle_lanes(ff):
+    """ff_server_reserve gives every lane a workspace for the stated batch up front; frames
+    and batches that fit it then run without any workspace growing (the footprint stays
+    put), with the same results as ff_fuse; a budget too small for every lane stops with
+    FF_ERR_OOM after the lanes that fit."""
+    print("[case] reserve", flush=True)
+    big, small = cached_frame("c2"), cached_frame("c1")
+    db, ds = ff.to_device(big), ff.to_device(small)
+    ref_b, ref_s = _alone(ff, db), _alone(ff, ds)
+    px, nc = big.pixels, len(big.cams)
+    want = 2 * px + (2 * px) // 4          # two large frames, with the lanes' pixel headroom
+    lane = int(ff.lib().ff_workspace_bytes(want, 2 * nc, 2))
+    srv = ff.Server(hbm_budget_bytes=4 * lane, lanes=3, max_batch_frames=2)
+    with pytest.raises(ff.FuseFlowError) as e:
+        srv.reserve(px, nc, 3)                               # beyond the batch limit
+    assert e.value.status == ff.FF_ERR_INVALID_ARG
+    srv.reserve(2 * px, 2 * nc, 2)
+    used = srv.stats()["hbm_used_bytes"]
+    assert used == 3 * lane
+    outs = []
+    for rep in range(2):
+        for name, d, P in (("b", db, big.pixels), ("s", ds, small.pixels), ("b", db, big.pixels)):
+            o = ff.Output(P, rgb=True)
+            srv.submit(rep, d, o)
+            outs.append((name, o))
+    srv.drain()
+    st = srv.stats()
+    assert st["frames"] == 6 and st["hbm_used_bytes"] == used and st["hbm_peak_bytes"] == used
+    for name, o in outs:
+        g, r = o.result(), (ref_s if name == "s" else ref_b)
+        for k in KEYS:
+            assert np.array_equal(g[k], r[k]), (name, k)
+    srv.close()
+    one = int(ff.lib().ff_workspace_bytes(px + px // 4, nc, 1))
+    two = ff.Server(hbm_budget_bytes=2 * one + one // 2, lanes=3, max_batch_frames=1)
+    with pytest.raises(ff.FuseFlowError) as e:
+        two.reserve(px, nc, 1)
+    assert e.value.status == ff.FF_ERR_OOM
+    assert two.stats()["hbm_used_bytes"] == 2 * one
+    o = ff.Output(big.pixels, rgb=True)
+    two.submit(0, db, o)
+    two.drain()
+    assert np.array_equal(o.result()["keys"], ref_b["keys"])
+    two.close()
+
+
 def test_server_admits_by_each_frames_footprint(ff):
     """The budget holds one large frame's workspace or several small ones, not both: small
     frames run side by side on the lanes, a large frame waits until they are done (idle
