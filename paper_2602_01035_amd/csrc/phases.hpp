@@ -1198,12 +1198,33 @@ __device__ __forceinline__ void ph_radix_up(const Ctx& C, uint32_t pass, uint32_
     uint32_t* s_h = reinterpret_cast<uint32_t*>(smem);
     for (uint32_t d = threadIdx.x; d < D; d += kBlock) s_h[d] = 0;
     __syncthreads();
+    if (!key64) {
+        // a histogram does not care about order: each thread counts ITEMS consecutive keys,
+        // read as 16-byte vectors (2 KiB per wave load instead of 256 bytes)
+        const uint32_t* kp = reinterpret_cast<const uint32_t*>(from_b ? C.keysB : C.keysA);
+        const uint32_t b = tile * KT + threadIdx.x * ITEMS;
+        if (b + ITEMS <= n) {
+            typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+            u4 v[ITEMS / 4];
+#pragma unroll
+            for (int q = 0; q < ITEMS / 4; ++q) v[q] = glob(reinterpret_cast<const u4*>(kp + b))[q];
+#pragma unroll
+            for (int q = 0; q < ITEMS / 4; ++q) {
+                atomicAdd(&s_h[(v[q].x >> shift) & (D - 1)], 1u);
+                atomicAdd(&s_h[(v[q].y >> shift) & (D - 1)], 1u);
+                atomicAdd(&s_h[(v[q].z >> shift) & (D - 1)], 1u);
+                atomicAdd(&s_h[(v[q].w >> shift) & (D - 1)], 1u);
+            }
+        } else {
+            for (int i = 0; i < ITEMS; ++i)
+                if (b + (uint32_t)i < n) atomicAdd(&s_h[(glob(kp)[b + i] >> shift) & (D - 1)], 1u);
+        }
+    } else {
 #pragma unroll 4
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t idx = tile * KT + (uint32_t)i * kBlock + threadIdx.x;
-        const bool in = idx < n;
-        const uint32_t dg = in ? (uint32_t)(load_key(C, from_b, key64, idx) >> shift) & (D - 1) : 0u;
-        if (in) atomicAdd(&s_h[dg], 1u);          // a histogram: order does not matter
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t idx = tile * KT + (uint32_t)i * kBlock + threadIdx.x;
+            if (idx < n) atomicAdd(&s_h[(uint32_t)(load_key(C, from_b, true, idx) >> shift) & (D - 1)], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < D; d += kBlock) C.digit_hist[(uint64_t)d * nt + tile] = s_h[d];
@@ -1363,20 +1384,38 @@ __device__ __forceinline__ uint64_t sorted_key(const Ctx& C, uint32_t i) {
 // Cells are runs of equal keys in sorted order: count the run heads per tile, scan, write
 // each cell's first position, and record where each frame's cells begin.
 
-// A sort tile walked wave-striped: wave w takes the tile's w-th quarter, lane l the keys
-// quarter + 64 i + l, so every load of a wave is contiguous.  Bit l of the ballot: key
-// i of lane l starts a run.
+// Thread t of a sort tile takes the tile's ITEMS consecutive sorted keys from
+// first = tile * 256 ITEMS + t ITEMS (32-bit keys read as 16-byte vectors).  Bit i of the
+// returned flags: key first + i starts a run (it is the first key, or differs from the key
+// before it).  The keys (k) and the key before them (prev) are returned for the head
+// writer's frame test.
 template <int ITEMS>
-__device__ __forceinline__ uint32_t head_idx(uint32_t tile, int i) {
-    return tile * (kBlock * ITEMS) + (threadIdx.x >> 6) * (64u * ITEMS) + (uint32_t)i * 64u +
-           lane_id();
-}
-template <int ITEMS>
-__device__ __forceinline__ uint64_t head_ballot(const Ctx& C, uint32_t tile, int i, uint32_t n) {
-    const uint32_t idx = head_idx<ITEMS>(tile, i);
-    bool h = false;
-    if (idx < n) h = idx == 0 || sorted_key(C, idx - 1) != sorted_key(C, idx);
-    return __ballot(h);
+__device__ __forceinline__ uint32_t head_flags(const Ctx& C, uint32_t tile, uint32_t n,
+                                               uint32_t& first, uint64_t (&k)[ITEMS],
+                                               uint64_t& prev) {
+    first = tile * (kBlock * ITEMS) + threadIdx.x * ITEMS;
+    if (first >= n) return 0u;
+    const bool key64 = C.bs->key64, from_b = C.bs->npass & 1;
+    prev = first == 0 ? 0ull : load_key(C, from_b, key64, first - 1);
+    if (!key64 && first + ITEMS <= n) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        const u4* kp = reinterpret_cast<const u4*>(
+            reinterpret_cast<const uint32_t*>(from_b ? C.keysB : C.keysA) + first);
+#pragma unroll
+        for (int q = 0; q < ITEMS / 4; ++q) {
+            const u4 v = glob(kp)[q];
+            k[4 * q] = v.x; k[4 * q + 1] = v.y; k[4 * q + 2] = v.z; k[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            k[i] = first + (uint32_t)i < n ? load_key(C, from_b, key64, first + i) : 0ull;
+    }
+    uint32_t flags = first == 0 ? 1u : (k[0] != prev ? 1u : 0u);
+#pragma unroll
+    for (int i = 1; i < ITEMS; ++i)
+        if (first + (uint32_t)i < n && k[i] != k[i - 1]) flags |= 1u << i;
+    return flags;
 }
 
 template <int ITEMS>
@@ -1384,10 +1423,10 @@ __device__ __forceinline__ void ph_head_count(const Ctx& C, uint32_t tile, char*
     if (C.hdr->prm.flags & 4u) return;
     const uint32_t n = n_keys(C);
     if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) c += (uint32_t)__popcll(head_ballot<ITEMS>(C, tile, i, n));
-    const uint32_t tot = block_sum(lane_id() == 0 ? c : 0u, reinterpret_cast<uint32_t*>(smem));
+    uint32_t first;
+    uint64_t k[ITEMS], prev;
+    const uint32_t c = (uint32_t)__popc(head_flags<ITEMS>(C, tile, n, first, k, prev));
+    const uint32_t tot = block_sum(c, reinterpret_cast<uint32_t*>(smem));
     if (threadIdx.x == 0) C.head_cnt[tile] = tot;
 }
 
@@ -1440,34 +1479,26 @@ __device__ __forceinline__ void ph_head_write(const Ctx& C, uint32_t tile, char*
     if (tile >= n_sort_tiles_real<ITEMS>(C)) return;
     uint64_t* s_fbeg = reinterpret_cast<uint64_t*>(smem);               // [F]
     uint32_t* s_w = reinterpret_cast<uint32_t*>(s_fbeg + kMaxFrames);   // [4]
-    const uint32_t nf = H.n_frames, w = threadIdx.x >> 6, l = lane_id();
+    const uint32_t nf = H.n_frames;
     for (uint32_t f = threadIdx.x; f < nf; f += kBlock) s_fbeg[f] = C.fs[f].fine_begin;
-    uint64_t m[ITEMS];
-    uint32_t c = 0;
+    uint32_t first;
+    uint64_t k[ITEMS], prev;
+    const uint32_t flags = head_flags<ITEMS>(C, tile, n, first, k, prev);
+    uint32_t tot;
+    // the tile's cells are numbered in key order: thread order, then bit order
+    uint32_t pos = C.head_cnt[tile] + block_excl((uint32_t)__popc(flags), s_w, tot);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        m[i] = head_ballot<ITEMS>(C, tile, i, n);
-        c += (uint32_t)__popcll(m[i]);
-    }
-    if (l == 0) s_w[w] = c;
-    __syncthreads();
-    uint32_t o = C.head_cnt[tile];
-    for (uint32_t v = 0; v < w; ++v) o += s_w[v];
-    const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (m[i] >> l & 1ull) {
-            const uint32_t idx = head_idx<ITEMS>(tile, i);
-            const uint32_t pos = o + (uint32_t)__popcll(m[i] & lt);
-            if (pos < C.P_cap) C.cell_start[pos] = idx; else raise_error(C.bs, kErrBounds);
-            // the first cell of a frame: the previous element belongs to another frame
-            const int f = frame_of_key(s_fbeg, (int)nf, sorted_key(C, idx));
-            if (idx == 0 || frame_of_key(s_fbeg, (int)nf, sorted_key(C, idx - 1)) != f) {
-                C.fs[f].cell_begin = pos;
-                C.fs[f].has_cells = 1;
-            }
+        if (!(flags >> i & 1u)) continue;
+        const uint32_t idx = first + (uint32_t)i;
+        if (pos < C.P_cap) C.cell_start[pos] = idx; else raise_error(C.bs, kErrBounds);
+        // the first cell of a frame: the previous element belongs to another frame
+        const int f = frame_of_key(s_fbeg, (int)nf, k[i]);
+        if (idx == 0 || frame_of_key(s_fbeg, (int)nf, i == 0 ? prev : k[i - 1]) != f) {
+            C.fs[f].cell_begin = pos;
+            C.fs[f].has_cells = 1;
         }
-        o += (uint32_t)__popcll(m[i]);
+        ++pos;
     }
 }
 
