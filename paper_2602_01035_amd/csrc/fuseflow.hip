@@ -605,11 +605,16 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     H->sort_items = (uint32_t)T.sort_items;
     H->hist_tiles = (uint32_t)T.hist_tiles;
     H->n_sort_tiles = (uint32_t)std::max<uint64_t>(1, (P + KT - 1) / KT);
-    // per-cell phase: waves walk 64-cell steps; at most the workgroups that fit resident
-    // at once (4 per CU at its register use), so no partial second round trails the launch
-    H->n_cell_items = T.cell_groups > 0
-                          ? (uint32_t)T.cell_groups
-                          : (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096));
+    // per-cell phase: waves walk 64-cell steps.  Up to one 8x1280x720 frame: at most the
+    // workgroups that fit resident at once (4 per CU at its register use), so no partial
+    // second round trails the launch; larger batches: one workgroup per 7200 pixels up to
+    // two rounds, which balances their uneven cells better (measured: 1024 best for one such
+    // frame, 2048 for two)
+    H->n_cell_items =
+        T.cell_groups > 0 ? (uint32_t)T.cell_groups
+        : P <= 1024ull * 7200ull
+            ? (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096))
+            : (uint32_t)std::min<uint64_t>(2048, (P + 7199) / 7200);
     H->max_radix_bits = (uint32_t)T.radix_bits;
     // Widest possible dense key.  The key range T is the sum over occupied coarse cells of
     // 8^L.  A cell refined to level L >= 1 holds more than target 4^(L-1) points (level L-1
@@ -1381,7 +1386,7 @@ ff_status ff_autotune(ff_context* c, int32_t n_frames, const ff_frame* frames,
         if (ms < best_ms) { best_ms = ms; best = t; }
     }
     const ff_tuning after_hist = best;
-    for (int cg : {0, 512, 768, 1536, 2048}) {
+    for (int cg : {0, 768, 1024, 1536, 2048, 3072}) {
         if (st != FF_OK) break;
         ff_tuning t = after_hist;
         t.cell_groups = cg;
