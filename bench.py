@@ -72,16 +72,17 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 
 
 # Hardware byte counters of the dominant kernel, from two rocprofv3 --pmc passes (FETCH_SIZE,
-# then WRITE_SIZE) over the single-frame launches of the 8x1280x720 workload (the frame-size
-# and trace legs, which run before any batch), each scaled by
-# what the same counter reads for a plain copy kernel of known size (1 GiB read, 1 GiB
-# written: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB).  Valid only for the kernel
-# sources they were taken on (their digest); otherwise the traffic is reported as null.
+# then WRITE_SIZE) over the launches that the roofline region times: batched calls of two
+# 8x1280x720 frames.  Each pass is scaled by what the same counter reads for a plain copy
+# kernel of known size (1 GiB read, 1 GiB written: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE
+# 1 GiB).  Valid only for the kernel sources they were taken on (their digest) and for
+# launches of that many frames; otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "df37c12b76f07e29",
-    "fetch_kib_per_frame": 91644.4,
-    "write_kib_per_frame": 54725.6,
+    "source_digest": "0bd39b0e8d881245",
+    "frames_per_launch": 2,
+    "fetch_kib_per_launch": 204135.8,
+    "write_kib_per_launch": 106731.7,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -656,10 +657,10 @@ def main():
     achieved = dom_bytes / (probe["total_ms"] * 1e-3) / 1e9
     fpl = probe["frames"] / max(1, probe["launches"])
     traffic = None
-    if COUNTERS["kernel"] == dom and COUNTERS["source_digest"] == kernel_source_digest():
-        per_frame = 1024 * (COUNTERS["fetch_kib_per_frame"] * COUNTERS["fetch_scale"] +
-                            COUNTERS["write_kib_per_frame"] * COUNTERS["write_scale"])
-        traffic = round(per_frame * fpl)
+    if (COUNTERS["kernel"] == dom and COUNTERS["source_digest"] == kernel_source_digest()
+            and abs(fpl - COUNTERS["frames_per_launch"]) < 1e-9):
+        traffic = round(1024 * (COUNTERS["fetch_kib_per_launch"] * COUNTERS["fetch_scale"] +
+                                COUNTERS["write_kib_per_launch"] * COUNTERS["write_scale"]))
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
