@@ -149,11 +149,13 @@ typedef struct ff_tuning {
     int32_t radix_bits;           /* widest digit of the LSD radix sort, 6..10 (the key bits
                                      are spread evenly over the fewest passes) */
     int32_t sort_items;           /* keys per thread per sort tile: 8 or 16 */
-    int32_t hist_tiles;           /* 4096-pixel tiles per coarse-histogram workgroup: 1..8 */
-    int32_t cell_groups;          /* workgroups of the per-cell phase, 64..4096, or 0: one
-                                     per 4096 pixels up to the 1024 resident at once for
-                                     batches of at most 7,372,800 pixels, else one per 7200
-                                     pixels up to 2048 */
+    int32_t hist_tiles;           /* 4096-pixel tiles per coarse-histogram workgroup: 1..8,
+                                     or 0 (default): about 900 workgroups, i.e. the batch's
+                                     tiles / 900 rounded, within 1..8 */
+    int32_t cell_groups;          /* workgroups of the per-cell phase, 64..4096, or 0
+                                     (default): the 1024 resident at once for batches of at
+                                     most 7,372,800 pixels, else one per 7200 pixels up to
+                                     2048 */
     int32_t use_graph;            /* 1: ff_fuse_batch replays a cached HIP graph (default) */
 } ff_tuning;
 

@@ -241,7 +241,7 @@ struct ff_context {
     hipEvent_t last = nullptr;
     bool have_last = false;
     std::vector<void*> allocs;
-    ff_tuning tune{8, 8, 4, 0, 1};                // default tuning
+    ff_tuning tune{8, 8, 0, 0, 1};                // default tuning
     std::map<std::string, ff_tuning> tuned;       // tuning per batch shape
     std::string device_name;
     hipStream_t cap_stream = nullptr;
@@ -430,7 +430,7 @@ std::string shape_key(int32_t n_frames, const ff_frame* frames, const ff_params*
 
 bool tuning_ok(const ff_tuning& t) {
     return t.radix_bits >= 6 && t.radix_bits <= kMaxRadixBits &&
-           (t.sort_items == 8 || t.sort_items == 16) && t.hist_tiles >= 1 &&
+           (t.sort_items == 8 || t.sort_items == 16) && t.hist_tiles >= 0 &&
            t.hist_tiles <= kMaxHistTiles && (t.cell_groups == 0 ||
            (t.cell_groups >= 64 && t.cell_groups <= 4096)) &&
            (t.use_graph == 0 || t.use_graph == 1);
@@ -603,18 +603,22 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
     H->n_scan_tiles = (uint32_t)std::max<uint64_t>(1, (ncounts + kScanTile - 1) / kScanTile);
     const uint32_t KT = (uint32_t)(kBlock * T.sort_items);
     H->sort_items = (uint32_t)T.sort_items;
-    H->hist_tiles = (uint32_t)T.hist_tiles;
+    // histogram tiles per workgroup: about 900 workgroups (3.5 per CU) measured fastest,
+    // from one 1280x720 camera (225 tiles: 1 each) to two 16-camera frames (8 each)
+    H->hist_tiles = T.hist_tiles > 0
+                        ? (uint32_t)T.hist_tiles
+                        : (uint32_t)std::min<uint64_t>(kMaxHistTiles,
+                                                       std::max<uint64_t>(1, (ntile + 450) / 900));
     H->n_sort_tiles = (uint32_t)std::max<uint64_t>(1, (P + KT - 1) / KT);
-    // per-cell phase: waves walk 64-cell steps.  Up to one 8x1280x720 frame: at most the
-    // workgroups that fit resident at once (4 per CU at its register use), so no partial
-    // second round trails the launch; larger batches: one workgroup per 7200 pixels up to
-    // two rounds, which balances their uneven cells better (measured: 1024 best for one such
-    // frame, 2048 for two)
-    H->n_cell_items =
-        T.cell_groups > 0 ? (uint32_t)T.cell_groups
-        : P <= 1024ull * 7200ull
-            ? (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, (P + 4095) / 4096))
-            : (uint32_t)std::min<uint64_t>(2048, (P + 7199) / 7200);
+    // per-cell phase: waves walk 64-cell steps.  Up to one 8x1280x720 frame: the workgroups
+    // that fit resident at once (4 per CU at its register use), so no partial second round
+    // trails the launch, and small frames still spread over every CU; larger batches: one
+    // workgroup per 7200 pixels up to two rounds, which balances their uneven cells better
+    // (measured: 1024 best for 1 to 8 such cameras, 2048 for two frames)
+    H->n_cell_items = T.cell_groups > 0 ? (uint32_t)T.cell_groups
+                      : P <= 1024ull * 7200ull
+                          ? 1024u
+                          : (uint32_t)std::min<uint64_t>(2048, (P + 7199) / 7200);
     H->max_radix_bits = (uint32_t)T.radix_bits;
     // Widest possible dense key.  The key range T is the sum over occupied coarse cells of
     // 8^L.  A cell refined to level L >= 1 holds more than target 4^(L-1) points (level L-1
@@ -1377,7 +1381,7 @@ ff_status ff_autotune(ff_context* c, int32_t n_frames, const ff_frame* frames,
         if (st != FF_OK) break;
     }
     const ff_tuning after_sort = best;
-    for (int h : {1, 2, 4, 8}) {
+    for (int h : {0, 1, 2, 4, 8}) {
         if (st != FF_OK) break;
         ff_tuning t = after_sort;
         t.hist_tiles = h;
