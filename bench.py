@@ -79,10 +79,10 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # launches of that many frames; otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "0bd39b0e8d881245",
+    "source_digest": "cc4c458c7df94a6b",
     "frames_per_launch": 2,
-    "fetch_kib_per_launch": 204135.8,
-    "write_kib_per_launch": 106731.7,
+    "fetch_kib_per_launch": 204054.3,
+    "write_kib_per_launch": 101484.7,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
