@@ -85,7 +85,12 @@ COUNTERS = {
     "write_kib_per_launch": 101484.7,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
+    # SQ_INSTS_VALU of the same launches (rocprofv3 --pmc): VALU wave-instructions issued
+    "valu_wave_instr_per_launch": 124.32e6,
 }
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU instruction per SIMD every
+# 4 cycles (16 lanes wide; packed FP32 disabled)
+VALU_PEAK_G_PER_S = 256 * 4 * 2.4 / 4
 
 
 def kernel_source_digest():
@@ -661,12 +666,17 @@ def main():
             and abs(fpl - COUNTERS["frames_per_launch"]) < 1e-9):
         traffic = round(1024 * (COUNTERS["fetch_kib_per_launch"] * COUNTERS["fetch_scale"] +
                                 COUNTERS["write_kib_per_launch"] * COUNTERS["write_scale"]))
+    valu = None
+    if traffic is not None:
+        g = COUNTERS["valu_wave_instr_per_launch"] / (mean_launch_ms * 1e-3) / 1e9
+        valu = {"achieved": round(g, 1), "peak": VALU_PEAK_G_PER_S,
+                "unit": "G VALU wave-instructions/s", "frac": round(g / VALU_PEAK_G_PER_S, 4)}
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "alg_bytes_per_launch": dom_bytes / max(1, probe["launches"]),
                 "mean_launch_ms": round(mean_launch_ms, 5), "launches": probe["launches"],
-                "frames_per_launch": fpl}
+                "frames_per_launch": fpl, "valu_issue": valu}
     B_frame = frame_alg_bytes(P, z["M"], z["S"], z["R"], K)
     B_timed = sum(frame_alg_bytes(P, sizes[k]["M"], sizes[k]["S"], sizes[k]["R"], K)
                   for s in range(args.steps) for k in step_frames(s))
