@@ -26,6 +26,7 @@
 // The plain baseline (config.plain = 1) runs the same trace one frame at a time through
 // ff_fuse and starts a frame only after the previous one completed.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -346,6 +347,10 @@ void ff_server::complete(Lane& L, double t, ff_status st) {
 
 void ff_server::run() {
     (void)hipSetDevice(device);
+    // the scheduler polls running batches every few microseconds: with the kernel's default
+    // 50 us timer slack each such sleep would last ~55 us, which delays both the detection of
+    // a completed frame and the launch of the next batch on its lane
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
         bool progressed = false;
