@@ -1115,14 +1115,19 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
         kv[k] = fbase[cc.lin] +
                 ((((uint64_t)loc[2] << L) | (uint64_t)loc[1]) << L | (uint64_t)loc[0]);
     });
-    // ranks in pixel order: group-major, then thread, then j
+    // ranks in pixel order: group-major, then thread, then j.  One scan of the four group
+    // counts packed in 16-bit fields (a group holds at most 1024 points per tile)
+    uint64_t packed = 0;
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi)
+        packed |= (uint64_t)__popc((mask >> (gi * 4)) & 0xFu) << (16 * gi);
+    uint64_t ptot;
+    const uint64_t pex = block_excl64(packed, reinterpret_cast<uint64_t*>(s_w), ptot);
     uint32_t off[4], tile_total = 0;
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
-        const uint32_t c = __popc((mask >> (gi * 4)) & 0xFu);
-        uint32_t tot;
-        off[gi] = tile_total + block_excl(c, s_w, tot);
-        tile_total += tot;
+        off[gi] = tile_total + (uint32_t)((pex >> (16 * gi)) & 0xFFFFu);
+        tile_total += (uint32_t)((ptot >> (16 * gi)) & 0xFFFFu);
     }
     // the frame's first compacted position: the points of the frames before it (each wave
     // sums them itself; at most kMaxFrames counts)
