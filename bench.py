@@ -462,8 +462,16 @@ def main():
               "communication)", file=sys.stderr)
         sys.exit(2)
 
-    # the 16-camera sequence renders in worker processes (started before anything touches
-    # the GPU) while this one renders the headline frames
+    import numpy as np
+    import torch
+    # counting devices does not initialise the GPU; the render workers below are started
+    # before anything does (a process that has initialised the GPU starts no programs)
+    if torch.cuda.device_count() == 0:
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+
+    # the 16-camera sequence renders in worker processes (they import only NumPy and the
+    # scene generator) while this one renders the headline frames
     c4_jobs, pool = [], None
     if not args.no_regimes or not args.no_cpu_baseline:
         import concurrent.futures as cf
@@ -471,10 +479,8 @@ def main():
         pool = cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1),
                                       mp_context=mp.get_context("spawn"))
         n4 = C4_FRAMES if not args.no_regimes else 1
+        # each submit starts a worker until there are max_workers: all exist after this
         c4_jobs = [pool.submit(render_inputs, "c4", i) for i in range(n4)]
-
-    import numpy as np
-    import torch
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(2)
