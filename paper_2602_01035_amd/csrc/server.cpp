@@ -10,10 +10,13 @@
 //
 // Admission is by device-memory footprint: the lanes' workspaces together stay within the
 // server's budget.  A lane's workspace is sized by the batches it has run (grown when a
-// batch needs more, with the budget's consent); a frame joins a batch only while the
-// batch's workspace fits what the other lanes leave of the budget, so a small frame never
-// reserves room for a large one, and a large frame waits until room is free (idle lanes
-// give theirs back when the head of the queue does not fit anywhere).
+// batch needs more, with the budget's consent) or made up front by ff_server_reserve; a
+// frame joins a batch only while the batch's workspace fits what the other lanes leave of
+// the budget, so a small frame never reserves room for a large one, and a large frame waits
+// until room is free (idle lanes give theirs back when the head of the queue does not fit
+// anywhere).  The head of the queue prefers a free lane that holds it as it is (the one that
+// last ran its rig first, whose graphs for that shape are cached), then an empty lane, then
+// the largest other one, since growing a lane re-creates its workspace.
 //
 // Ordering with the caller: at submit an event is recorded on the caller's stream, and
 // the lane waits for it before the frame's batch runs, so work the caller queued before
