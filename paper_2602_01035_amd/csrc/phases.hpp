@@ -1745,34 +1745,40 @@ __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
     return max(min(a, b), min(max(a, b), c));
 }
 
-// The three largest confidence values t0 >= t1 >= t2 of a set (0 = empty slot), kept by
-// a three-instruction insertion network.  `tie` is set whenever a value equal to a kept
-// one is met: only then can the position / pixel tie-break of the full order change the
-// choice or the order of the three, and the caller ranks that cell again in full.  Without
-// a tie each of the three values belongs to exactly one member.
-struct Top3v {
-    uint32_t t0, t1, t2;
+// The three largest confidence values t0 >= t1 >= t2 of a set (0 = empty slot) and the
+// sorted positions k0, k1, k2 of the members that hold them (kPad for an empty slot), kept
+// by a three-instruction insertion network plus one select per position.  `tie` is set
+// whenever a value equal to a kept one is met: only then can the position / pixel
+// tie-break of the full order change the choice or the order of the three, and the caller
+// ranks that cell again in full.  Without a tie each of the three values belongs to
+// exactly one member, whose position is the one kept beside it.
+struct Top3p {
+    uint32_t t0, t1, t2, k0, k1, k2;
     bool tie;
 };
-__device__ __forceinline__ void top3v_push(Top3v& t, uint32_t v) {
+__device__ __forceinline__ void top3p_push(Top3p& t, uint32_t v, uint32_t k) {
     t.tie |= (v != 0u) & ((v == t.t0) | (v == t.t1) | (v == t.t2));
+    const bool g0 = v > t.t0, g1 = v > t.t1, g2 = v > t.t2;
+    const uint32_t nk0 = g0 ? k : t.k0;
+    const uint32_t nk1 = g0 ? t.k0 : (g1 ? k : t.k1);
+    const uint32_t nk2 = g1 ? t.k1 : (g2 ? k : t.k2);
     const uint32_t n0 = max(t.t0, v), n1 = med3u(t.t0, t.t1, v), n2 = med3u(t.t1, t.t2, v);
     t.t0 = n0;
     t.t1 = n1;
     t.t2 = n2;
+    t.k0 = nk0;
+    t.k1 = nk1;
+    t.k2 = nk2;
 }
 // merge the partner lane's three (disjoint members) into this lane's
 template <int CTRL>
-__device__ __forceinline__ void top3v_merge(Top3v& t) {
+__device__ __forceinline__ void top3p_merge(Top3p& t) {
     const uint32_t a = qmov<CTRL>(t.t0), b = qmov<CTRL>(t.t1), c = qmov<CTRL>(t.t2);
+    const uint32_t ka = qmov<CTRL>(t.k0), kb = qmov<CTRL>(t.k1), kc = qmov<CTRL>(t.k2);
     t.tie |= qmov<CTRL>(t.tie ? 1u : 0u) != 0u;
-    top3v_push(t, a);
-    top3v_push(t, b);
-    top3v_push(t, c);
-}
-template <int CTRL>
-__device__ __forceinline__ uint32_t qmin(uint32_t v) {
-    return min(v, qmov<CTRL>(v));
+    top3p_push(t, a, ka);
+    top3p_push(t, b, kb);
+    top3p_push(t, c, kc);
 }
 
 // Output of one cell from its representatives' values: joint weights w = C V (Eq. 10) and
@@ -1984,15 +1990,15 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
             if (ok) {
                 // this lane's members start + q, start + q + 4, ...: confidences of 4 of
                 // them are loaded together (most cells give a lane one or two members),
-                // then ranked by value; a second pass over the same members finds which
-                // of them hold the three values (unique unless a tie was seen)
+                // then ranked by value with their positions carried along; the positions
+                // are the representatives unless a tie was seen
                 auto conf_at = [&](uint32_t k) -> float {
                     if (have_cs) return __uint_as_float(glob(C.conf_sorted)[k]);
                     const uint32_t id = glob(vals)[k];
                     const CamLite& cm = cams[last_le(s_cam_pix, (int)nc, id)];
                     return glob(cm.conf)[id - cm.pix_off];
                 };
-                Top3v t{0u, 0u, 0u, no_mf};           // all confidences 1: full order
+                Top3p t{0u, 0u, 0u, kPad, kPad, kPad, no_mf};   // all confidences 1: full order
                 if (!no_mf) {
                     for (uint32_t k0 = start + q; k0 < end; k0 += 16u) {
                         float cv[4];
@@ -2004,35 +2010,19 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const uint32_t k = k0 + 4u * u;
-                            if (k < end) top3v_push(t, conf_bits(cv[u]));
+                            if (k < end) top3p_push(t, conf_bits(cv[u]), k);
                         }
                     }
                 }
-                top3v_merge<kQuadXor1>(t);
-                top3v_merge<kQuadXor2>(t);
+                top3p_merge<kQuadXor1>(t);
+                top3p_merge<kQuadXor2>(t);
                 const int nrep = (int)min(3u, end - start);
                 uint32_t kr0 = kPad, kr1 = kPad, kr2 = kPad;
                 float cr0 = o2f(t.t0), cr1 = o2f(t.t1), cr2 = o2f(t.t2);
                 if (!t.tie) {
-                    for (uint32_t k0 = start + q; k0 < end; k0 += 16u) {
-                        float cv[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const uint32_t k = k0 + 4u * u;
-                            cv[u] = k < end ? conf_at(k) : 0.0f;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const uint32_t k = k0 + 4u * u;
-                            const uint32_t v = k < end ? conf_bits(cv[u]) : 0u;
-                            kr0 = (v != 0u && v == t.t0) ? k : kr0;
-                            kr1 = (v != 0u && v == t.t1) ? k : kr1;
-                            kr2 = (v != 0u && v == t.t2) ? k : kr2;
-                        }
-                    }
-                    kr0 = qmin<kQuadXor1>(kr0); kr0 = qmin<kQuadXor2>(kr0);
-                    kr1 = qmin<kQuadXor1>(kr1); kr1 = qmin<kQuadXor2>(kr1);
-                    kr2 = qmin<kQuadXor1>(kr2); kr2 = qmin<kQuadXor2>(kr2);
+                    kr0 = t.k0;
+                    kr1 = t.k1;
+                    kr2 = t.k2;
                 } else {
                     // equal confidences among the best: lane 0 ranks the whole cell in the
                     // full order (confidence, then position, then pixel id)
