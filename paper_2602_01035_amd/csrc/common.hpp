@@ -18,6 +18,7 @@ constexpr int kMaxBatchCams = 1024;
 constexpr int kMaxFrames = 64;
 constexpr int kRSlots = 16;              // spread counters for representatives per frame
 constexpr int kHashSlots = 2048;         // LDS hash of the coarse histogram
+constexpr int kCountStripes = 4;         // copies of the coarse counts the histogram adds into
 constexpr int kLdsCams = 256;            // cameras staged in LDS by the per-cell phase
 constexpr int kEMin = -24, kEMax = 100;  // clamp of the coarse exponent
 constexpr uint32_t kPad = 0xFFFFFFFFu;

@@ -397,7 +397,7 @@ ff_status grow_counts(ff_context* c, uint64_t need, hipStream_t stream) {
     c->counts = nullptr; c->fine_base = nullptr; c->level = nullptr; c->cls = nullptr;
     c->scan_tile = nullptr;
     ff_status st;
-    if ((st = dalloc(c, (void**)&c->counts, need * 4)) != FF_OK) return st;
+    if ((st = dalloc(c, (void**)&c->counts, need * 4 * kCountStripes)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->fine_base, need * 8)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->level, need)) != FF_OK) return st;
     if ((st = dalloc(c, (void**)&c->cls, need * sizeof(CamClass))) != FF_OK) return st;
@@ -961,7 +961,7 @@ void ff_params_default(ff_params* p) {
 uint64_t ff_workspace_bytes(uint64_t max_pixels, int32_t max_cameras, int32_t max_frames) {
     const Sizes s = sizes_for(max_pixels, max_cameras, max_frames);
     return s.desc + sizeof(BatchState) + sizeof(FrameState) * (uint64_t)max_frames +
-           s.px_tiles * (sizeof(TilePart) + 4) + s.counts * (13 + sizeof(CamClass)) +
+           s.px_tiles * (sizeof(TilePart) + 4) + s.counts * (4 * kCountStripes + 9 + sizeof(CamClass)) +
            s.scan * 8 + 2 * s.keys * 12 +
            s.dhist * 4 + kMaxDigits * 4 + s.sort_tiles * 4 + s.cell * 4 + s.keys * 4 +
            sizeof(CamLite) * (uint64_t)max_cameras + (max_pixels + max_cameras + 64) * 4 +
@@ -1030,7 +1030,8 @@ ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
     if ((st = dalloc(c, (void**)&c->fs, sizeof(FrameState) * max_frames)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->tiles, sizeof(TilePart) * s.px_tiles)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->tile_off, 4 * s.px_tiles)) != FF_OK) return fail(st);
-    if ((st = dalloc(c, (void**)&c->counts, s.counts * 4)) != FF_OK) return fail(st);
+    if ((st = dalloc(c, (void**)&c->counts, s.counts * 4 * kCountStripes)) != FF_OK)
+        return fail(st);
     if ((st = dalloc(c, (void**)&c->fine_base, s.counts * 8)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->level, s.counts)) != FF_OK) return fail(st);
     if ((st = dalloc(c, (void**)&c->cls, s.counts * sizeof(CamClass))) != FF_OK) return fail(st);

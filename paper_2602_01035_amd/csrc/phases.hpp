@@ -577,17 +577,17 @@ __device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem
 
 // ---------------------------------------------------------------- phase: back-project + AABB
 // Eq. 8-9 per pixel, and the extents of Sec. II.5(1)b as per-tile partials (no atomics).
-// Also clears this tile's share of the coarse histogram for the next phases.
+// Also clears this tile's share of the coarse histogram's copies for the next phases.
 
 __device__ __forceinline__ void ph_backproject(const Ctx& C, uint32_t tile, char* smem) {
     const CallHdr& H = *C.hdr;
     const DevParams& P = H.prm;
     const uint32_t tid = threadIdx.x;
     if (!(P.flags & 4u)) {
-        const uint32_t nc = H.n_counts;
-        const uint32_t chunk = (nc + H.n_px_tiles - 1) / H.n_px_tiles;
-        const uint32_t b0 = tile * chunk, b1 = min(nc, b0 + chunk);
-        for (uint32_t i = b0 + tid; i < b1; i += kBlock) C.counts[i] = 0;
+        const uint64_t nc = (uint64_t)H.n_counts * kCountStripes;
+        const uint64_t chunk = (nc + H.n_px_tiles - 1) / H.n_px_tiles;
+        const uint64_t b0 = (uint64_t)tile * chunk, b1 = min(nc, b0 + chunk);
+        for (uint64_t i = b0 + tid; i < b1; i += kBlock) C.counts[i] = 0;
     }
     const DevCam& cm = C.cams[cam_of_tile(C, tile)];
     const float* rx = C.raytab + cm.tab_off;
@@ -714,7 +714,10 @@ __device__ __forceinline__ void ph_tile_reduce(const Ctx& C, uint32_t f, char* s
 // ---------------------------------------------------------------- phase: coarse histogram
 // Sec. II.5(1)c.  Counts are merged per thread (4 neighbouring pixels), then per run of
 // lanes with the same cell (a wave scan), accumulated in an LDS hash of the tile's cells,
-// and one global atomic per distinct cell and tile goes out at the end.
+// and one global atomic per distinct cell and tile goes out at the end.  A frame occupies
+// only a few thousand coarse cells, so those atomics meet on few addresses, and device-
+// scope atomics on one address serialise: workgroup w adds into copy w mod kCountStripes
+// of the counts, and the first scan phase folds the copies into copy 0.
 
 // one pixel tile into the LDS hash (counts: the frame's, for the rare full-hash case)
 __device__ __forceinline__ void hist_tile(const Ctx& C, const DevCam& cm, uint32_t tile,
@@ -807,9 +810,10 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem)
     const uint32_t t1 = min(t0 + H.hist_tiles, H.n_px_tiles);
     if (t0 >= t1) return;
     uint32_t frame = C.cams[cam_of_tile(C, t0)].frame;
+    uint32_t* const stripe = C.counts + (uint64_t)(item % kCountStripes) * H.n_counts;
     auto flush = [&](uint32_t f) {
         __syncthreads();
-        uint32_t* counts = C.counts + (uint64_t)f * G3;
+        uint32_t* counts = stripe + (uint64_t)f * G3;
         for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
             const uint32_t k = s_key[i];
             if (k != kPad) atomicAdd(&counts[k], s_cnt[i]);
@@ -835,7 +839,7 @@ __device__ __forceinline__ void ph_hist(const Ctx& C, uint32_t item, char* smem)
             flush(frame);
             frame = cm.frame;
         }
-        hist_tile(C, cm, tile, buf[i & 1], s_key, s_cnt, C.counts + (uint64_t)cm.frame * G3,
+        hist_tile(C, cm, tile, buf[i & 1], s_key, s_cnt, stripe + (uint64_t)cm.frame * G3,
                   no_mf);
     }
     flush(frame);
@@ -912,9 +916,9 @@ __device__ __forceinline__ void classify_box(const DevCam& cm, const double lo[3
 
 // ---------------------------------------------------------------- phase: coarse scan
 // span(c) = 8^L(c) dense fine indices for every occupied coarse cell; the exclusive scan
-// over (frame, cell) gives each cell's first dense index.  Three steps: tile sums, a
-// one-workgroup scan of the tile sums (which also fixes the sort's key width and passes),
-// and the per-tile scan.
+// over (frame, cell) gives each cell's first dense index.  Three steps: tile sums (which
+// also fold the histogram's copies of the counts), a one-workgroup scan of the tile sums
+// (which also fixes the sort's key width and passes), and the per-tile scan.
 
 __device__ __forceinline__ uint64_t span_of(uint32_t n, const DevParams& P) {
     return n ? (1ull << (3 * level_of(n, P))) : 0ull;
@@ -929,7 +933,13 @@ __device__ __forceinline__ void ph_scan_a(const Ctx& C, uint32_t tile, char* sme
 #pragma unroll 4
     for (int i = 0; i < kScanTile / kBlock; ++i) {
         const uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
-        if (idx < total) s += span_of(C.counts[idx], P);
+        if (idx < total) {
+            uint32_t n = 0;                    // fold the histogram's copies into copy 0
+#pragma unroll
+            for (int q = 0; q < kCountStripes; ++q) n += C.counts[idx + (uint64_t)q * total];
+            C.counts[idx] = n;
+            s += span_of(n, P);
+        }
     }
     uint64_t* s_w = reinterpret_cast<uint64_t*>(smem);
     s = wave_sum64(s);
