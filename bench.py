@@ -79,14 +79,14 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # launches of that many frames; otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "200f34f06aacc24b",
+    "source_digest": "d3a7e7f55c5cb4dd",
     "frames_per_launch": 2,
-    "fetch_kib_per_launch": 203653.8,
-    "write_kib_per_launch": 106812.5,
+    "fetch_kib_per_launch": 198612.6,
+    "write_kib_per_launch": 106460.6,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # SQ_INSTS_VALU of the same launches (rocprofv3 --pmc): VALU wave-instructions issued
-    "valu_wave_instr_per_launch": 124.29e6,
+    "valu_wave_instr_per_launch": 122.79e6,
 }
 # VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU instruction per SIMD every
 # 4 cycles (16 lanes wide; packed FP32 disabled)
