@@ -1245,6 +1245,31 @@ __device__ __forceinline__ void ph_radix_up(const Ctx& C, uint32_t pass, uint32_
     for (uint32_t d = threadIdx.x; d < D; d += kBlock) C.digit_hist[(uint64_t)d * nt + tile] = s_h[d];
 }
 
+// In-place exclusive scan of row[0, n) by one workgroup, for n <= kBlock * kRowScanPer:
+// thread t takes the ceil(n / kBlock) consecutive entries from t ceil(n / kBlock), and all
+// of its loads are in flight before the one block scan.  Returns the total.
+constexpr int kRowScanPer = 32;
+__device__ __forceinline__ uint32_t row_scan_one_step(uint32_t* row, uint32_t n, uint32_t* s_w) {
+    const uint32_t per = (n + kBlock - 1) / kBlock;
+    const uint32_t b = threadIdx.x * per;
+    uint32_t v[kRowScanPer], loc = 0;
+#pragma unroll
+    for (int j = 0; j < kRowScanPer; ++j) {
+        const uint32_t i = b + (uint32_t)j;
+        v[j] = ((uint32_t)j < per && i < n) ? row[i] : 0u;
+        loc += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl(loc, s_w, tot);
+#pragma unroll
+    for (int j = 0; j < kRowScanPer; ++j) {
+        const uint32_t i = b + (uint32_t)j;
+        if ((uint32_t)j < per && i < n) row[i] = run;
+        run += v[j];
+    }
+    return tot;
+}
+
 template <int ITEMS>
 __device__ __forceinline__ void ph_radix_scan(const Ctx& C, uint32_t pass, uint32_t d, char* smem) {
     BatchState* bs = C.bs;
@@ -1254,6 +1279,11 @@ __device__ __forceinline__ void ph_radix_scan(const Ctx& C, uint32_t pass, uint3
     const uint32_t nt = n_sort_tiles_real<ITEMS>(C);
     uint32_t* row = C.digit_hist + (uint64_t)d * nt;
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
+    if (nt <= (uint32_t)(kBlock * kRowScanPer)) {
+        const uint32_t tot = row_scan_one_step(row, nt, s_w);
+        if (threadIdx.x == 0) C.digit_total[d] = tot;
+        return;
+    }
     uint32_t carry = 0;
     constexpr int kPer = 8;                  // consecutive tiles per thread per step
     for (uint32_t b = 0; b < nt; b += kBlock * kPer) {
@@ -1450,9 +1480,10 @@ __device__ __forceinline__ void ph_head_scan(const Ctx& C, uint32_t, char* smem)
     if (C.hdr->prm.flags & 4u) return;
     const uint32_t n = n_keys(C), nt = n_sort_tiles_real<ITEMS>(C);
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
-    uint32_t carry = 0;
+    const bool one_step = nt <= (uint32_t)(kBlock * kRowScanPer);
+    uint32_t carry = one_step ? row_scan_one_step(C.head_cnt, nt, s_w) : 0u;
     constexpr int kPer = 8;                  // consecutive tiles per thread per step
-    for (uint32_t b = 0; b < nt; b += kBlock * kPer) {
+    for (uint32_t b = one_step ? nt : 0u; b < nt; b += kBlock * kPer) {
         uint32_t v[kPer], sum = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
