@@ -79,10 +79,10 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # launches of that many frames; otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "d3a7e7f55c5cb4dd",
+    "source_digest": "08cf02a4e260b126",
     "frames_per_launch": 2,
-    "fetch_kib_per_launch": 198612.6,
-    "write_kib_per_launch": 106460.6,
+    "fetch_kib_per_launch": 198534.9,
+    "write_kib_per_launch": 106475.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # SQ_INSTS_VALU of the same launches (rocprofv3 --pmc): VALU wave-instructions issued
