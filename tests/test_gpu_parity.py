@@ -487,3 +487,42 @@ def test_bad_arguments_raise(ctx, ff):
     for bad in _bad_cameras(dev["cams"][0]):
         with pytest.raises(ff.FuseFlowError):
             ctx.fuse([bad] + dev["cams"][1:], dev["depth"], dev["conf"])
+
+
+def _scattered_frame(seed, n_cams=4):
+    """Cameras of 64 x 64 px (one 4,096-px tile each, 90-degree field of view) with
+    independent random depths in [1, 30] m: under a 128^3 coarse grid nearly every pixel
+    lands in a coarse cell of its own, about 3,900 per camera."""
+    rng = np.random.default_rng(seed)
+    base = ring_cameras([(64, 64)] * n_cams, radius=3.0)
+    cams = [Camera(64, 64, 32.0, 32.0, 32.0, 32.0, c.world_to_cam) for c in base]
+    fr = make_frame(cams, _scene_c1(rng, cams), seed)
+    D = [rng.uniform(1.0, 30.0, (64, 64)).astype(np.float32) for _ in cams]
+    C = [rng.uniform(0.61, 1.0, (64, 64)).astype(np.float32) for _ in cams]
+    return dataclasses.replace(fr, depth=D, conf=C)
+
+
+@pytest.mark.parametrize("hist_tiles", [1, 2])
+def test_coarse_histogram_hash_overflow(ff, hist_tiles):
+    """Sec. II.5(1)c counts with more distinct coarse cells per histogram workgroup than its
+    LDS hash holds (2,048): the overflow goes straight to the global counts.  With two tiles
+    per workgroup a batched workgroup also spans two frames, whose counts it flushes apart."""
+    f = _scattered_frame(5, n_cams=3)          # 3 tiles per frame: pairs of tiles straddle
+    p = ff.Params(coarse_res=128)
+    op = oracle_params(p)
+    pts = O.generate_points([O.camera_f32(c) for c in f.cams], f.depth, f.conf, op)
+    lo, _ = O.extents(pts["xyz"])
+    e = O.coarse_exponent(*O.extents(pts["xyz"]), op.coarse_res)
+    lin = O.coarse_linear(O.coarse_cells(pts["xyz"], lo, e, op.coarse_res)[1], op.coarse_res)
+    cam = pts["pix"] // (64 * 64)
+    assert min(len(np.unique(lin[cam == k])) for k in range(len(f.cams))) > 2048
+    print(f"[case] coarse histogram hash overflow, {hist_tiles} tiles per workgroup", flush=True)
+    c = ff.Context(max_pixels=2 * 3 * 64 * 64, max_cameras=8, max_frames=2)
+    c.set_tuning(hist_tiles=hist_tiles)
+    d = ff.to_device(f)
+    o = O.fuse_frame(f, op)
+    compare(c.fuse(d["cams"], d["depth"], d["conf"], d["rgb"], params=p, members=True).result(),
+            o, label=f"overflow plain {hist_tiles}")
+    for k, out in enumerate(c.fuse_batch([d, d], params=p, members=True)):
+        compare(out.result(), o, label=f"overflow batched frame {k}, {hist_tiles}")
+    c.close()
