@@ -153,9 +153,9 @@ typedef struct ff_tuning {
                                      or 0 (default): about 900 workgroups, i.e. the batch's
                                      tiles / 900 rounded, within 1..8 */
     int32_t cell_groups;          /* workgroups of the per-cell phase, 64..4096, or 0
-                                     (default): the 1024 resident at once for batches of at
-                                     most 7,372,800 pixels, else one per 7200 pixels up to
-                                     2048 */
+                                     (default): as many as the device holds resident at
+                                     once for the launch (1280 on MI355X: 256 CUs x 5) for
+                                     batches of at most 7,372,800 pixels, else twice that */
     int32_t use_graph;            /* 1: ff_fuse_batch replays a cached HIP graph (default) */
 } ff_tuning;
 

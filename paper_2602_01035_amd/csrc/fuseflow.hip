@@ -244,6 +244,8 @@ struct ff_context {
     ff_tuning tune{8, 8, 0, 0, 1};                // default tuning
     std::map<std::string, ff_tuning> tuned;       // tuning per batch shape
     std::string device_name;
+    int n_cu = 0;                                 // compute units of the device
+    std::map<uint64_t, uint32_t> cells_fit;       // resident per-cell workgroups by launch shape
     hipStream_t cap_stream = nullptr;
     std::map<std::string, hipGraphExec_t> graphs;
     // kernel tracing (events on the call's stream)
@@ -490,6 +492,24 @@ struct Plan {
 
 // Validate one batch and fill the host staging descriptor.  Returns the launch plan and a
 // key describing everything the plan depends on (for the graph cache).
+// Workgroups of the per-cell kernel that the whole device holds at once for a launch shape
+// (kernel variant and LDS bytes): how many share a CU follows from their registers and LDS.
+uint32_t cells_resident(ff_context* c, bool wide, bool lds, size_t smem) {
+    const uint64_t key = ((uint64_t)(wide ? 2u : 0u) | (lds ? 1u : 0u)) << 32 | (uint64_t)smem;
+    const auto it = c->cells_fit.find(key);
+    if (it != c->cells_fit.end()) return it->second;
+    const void* f = wide ? (lds ? (const void*)k_cells<kMaxK - 1, true>
+                                : (const void*)k_cells<kMaxK - 1, false>)
+                         : (lds ? (const void*)k_cells<3, true> : (const void*)k_cells<3, false>);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, smem) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 4;
+    const uint32_t r = (uint32_t)std::max(1, c->n_cu > 0 ? c->n_cu : 256) * (uint32_t)per_cu;
+    c->cells_fit[key] = r;
+    return r;
+}
+
 ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
                      const ff_params* prm, const ff_output* outs, const ff_tuning& T,
                      char* stage, Plan& plan, std::string& shape) {
@@ -611,14 +631,16 @@ ff_status build_desc(ff_context* c, int32_t n_frames, const ff_frame* frames,
                                                        std::max<uint64_t>(1, (ntile + 450) / 900));
     H->n_sort_tiles = (uint32_t)std::max<uint64_t>(1, (P + KT - 1) / KT);
     // per-cell phase: waves walk 64-cell steps.  Up to one 8x1280x720 frame: the workgroups
-    // that fit resident at once (4 per CU at its register use), so no partial second round
-    // trails the launch, and small frames still spread over every CU; larger batches: one
-    // workgroup per 7200 pixels up to two rounds, which balances their uneven cells better
-    // (measured: 1024 best for 1 to 8 such cameras, 2048 for two frames)
-    H->n_cell_items = T.cell_groups > 0 ? (uint32_t)T.cell_groups
-                      : P <= 1024ull * 7200ull
-                          ? 1024u
-                          : (uint32_t)std::min<uint64_t>(2048, (P + 7199) / 7200);
+    // that fit resident at once (5 per CU at its register and LDS use, 1280), so no partial
+    // second round trails the launch, and small frames still spread over every CU; larger
+    // batches: two full rounds, which balance their uneven cells better (measured at two
+    // such frames: 2560 workgroups 130 us per frame, 2048 140, 1280 137)
+    {
+        const uint32_t resident = cells_resident(c, plan.wide_views, ncam <= (uint32_t)kLdsCams,
+                                                 cells_smem(ncam, (uint32_t)n_frames));
+        H->n_cell_items = T.cell_groups > 0 ? (uint32_t)T.cell_groups
+                          : P <= 7372800ull ? resident : 2u * resident;
+    }
     H->max_radix_bits = (uint32_t)T.radix_bits;
     // Widest possible dense key.  The key range T is the sum over occupied coarse cells of
     // 8^L.  A cell refined to level L >= 1 holds more than target 4^(L-1) points (level L-1
@@ -1006,6 +1028,7 @@ ff_status ff_context_create(ff_context** out, int device, uint64_t max_pixels,
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
             c->device_name = prop.name;
+            c->n_cu = prop.multiProcessorCount;
             for (char& ch : c->device_name)
                 if (ch == '"' || ch == '\\') ch = ' ';
         }
@@ -1391,7 +1414,7 @@ ff_status ff_autotune(ff_context* c, int32_t n_frames, const ff_frame* frames,
         if (ms < best_ms) { best_ms = ms; best = t; }
     }
     const ff_tuning after_hist = best;
-    for (int cg : {0, 768, 1024, 1536, 2048, 3072}) {
+    for (int cg : {0, 768, 1024, 1280, 2048, 2560, 3840}) {
         if (st != FF_OK) break;
         ff_tuning t = after_hist;
         t.cell_groups = cg;
