@@ -79,14 +79,14 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # launches of that many frames; otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "445d86e9def83c9e",
+    "source_digest": "9fed2305b2d8d51f",
     "frames_per_launch": 2,
-    "fetch_kib_per_launch": 201876.3,
-    "write_kib_per_launch": 106515.8,
+    "fetch_kib_per_launch": 203484.6,
+    "write_kib_per_launch": 106583.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # SQ_INSTS_VALU of the same launches (rocprofv3 --pmc): VALU wave-instructions issued
-    "valu_wave_instr_per_launch": 123.04e6,
+    "valu_wave_instr_per_launch": 118.27e6,
 }
 # VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU instruction per SIMD every
 # 4 cycles (16 lanes wide; packed FP32 disabled)

@@ -65,6 +65,7 @@ struct CamLite {
     uint32_t rank, pix_off;
     uint32_t frame;          // frame index in the batch
     uint32_t frame_cam;      // index of the camera within its frame (class mask bit)
+    uint32_t tab_off;        // this camera's ray table: W column rays, then H row rays
     float invW;              // 1 / W, for a quick first guess of y = pixel / W
     // field-of-view fast path: cx + 1/2, cy + 1/2, and the largest floats below
     // W - m, H - m (clearly inside) and W + m, H + m (not clearly outside), m = 1/16 px

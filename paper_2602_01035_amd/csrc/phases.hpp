@@ -562,6 +562,7 @@ __device__ __forceinline__ void ph_cam_prep(const Ctx& C, uint32_t i, char* smem
         cl.W = me.W; cl.H = me.H; cl.rank = rank; cl.pix_off = me.pix_off;
         cl.frame = me.frame;
         cl.frame_cam = i - fr.cam_begin;
+        cl.tab_off = cm.tab_off;
         cl.invW = 1.0f / (float)me.W;
         cl.cxh = me.cx + 0.5f;
         cl.cyh = me.cy + 0.5f;
@@ -1675,7 +1676,8 @@ __device__ __forceinline__ void insert_sorted(uint64_t (&s)[N], uint64_t c) {
 // (distance, rank).  A branch-free insertion keeps the KV smallest keys sorted.  A camera
 // no lane of the wave can see is skipped as a whole.
 template <int KV>
-__device__ __forceinline__ double neg_log_v(const CamLite* cams, uint32_t own_bit, const Pt& p,
+__device__ __forceinline__ double neg_log_v(const CamLite* cams, const float* raytab,
+                                            uint32_t own_bit, const Pt& p,
                                             uint32_t fcam0, uint32_t fcams, uint64_t in_all,
                                             uint64_t partial, const DevParams& P) {
     const int keep = (P.K < (int)fcams ? P.K : (int)fcams) - 1;
@@ -1709,12 +1711,12 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, uint32_t own_bi
         if (q < keep && best[q] != kNone) nb = q + 1;
     }
     // pixels of the kept views (the camera-frame point is recomputed: cheaper than carrying
-    // it), then their depths as independent gathers
+    // it), then their depths and pixel rays as independent gathers
     int bx[KV], by[KV];
-    float dv[KV];
+    float dv[KV], rxv[KV], ryv[KV];
 #pragma unroll
     for (int q = 0; q < KV; ++q) {
-        dv[q] = 0.0f;
+        dv[q] = rxv[q] = ryv[q] = 0.0f;
         bx[q] = by[q] = 0;
         if (q < nb) {
             const CamLite& cj = cams[bj[q]];
@@ -1723,6 +1725,9 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, uint32_t own_bi
             const float Z = ((cj.R[6] * p.x + cj.R[7] * p.y) + cj.R[8] * p.z) + cj.t[2];
             exact_pixel(cj, X, Y, Z, bx[q], by[q]);
             dv[q] = glob(cj.depth)[(uint32_t)by[q] * (uint32_t)cj.W + (uint32_t)bx[q]];
+            const float* rt = raytab + cj.tab_off;
+            rxv[q] = glob(rt)[bx[q]];
+            ryv[q] = glob(rt + cj.W)[by[q]];
         }
     }
     double s = 0.0;
@@ -1733,10 +1738,9 @@ __device__ __forceinline__ double neg_log_v(const CamLite* cams, uint32_t own_bi
         const float d = dv[q];
         if (!(__builtin_isfinite(d) && d > 0.0f)) continue;
         const CamLite& cj = cams[bj[q]];
-        // the ray of pixel (bx, by) as the quotients the ray tables hold (the same IEEE
-        // operations): two divisions are cheaper here than two more divergent gathers
-        const Pt Q = backproject_ray(cj, ((float)bx[q] - cj.cx) / cj.fx,
-                                     ((float)by[q] - cj.cy) / cj.fy, d);
+        // the ray of pixel (bx, by) from the camera's ray tables (the IEEE quotients
+        // (x - cx)/fx and (y - cy)/fy), loaded beside the depth: cheaper than two divisions
+        const Pt Q = backproject_ray(cj, rxv[q], ryv[q], d);
         // the differences of two floats and their squares are exact in double
         const double ex = (double)p.x - (double)Q.x;
         const double ey = (double)p.y - (double)Q.y;
@@ -2157,7 +2161,7 @@ __device__ __forceinline__ void ph_cells(const Ctx& C, uint32_t item, char* smem
                     in_all = kc->in_all;
                     partial = kc->partial;
                 }
-                expo = neg_log_v<KV>(cams, cm.frame_cam, mine.p, fr.cam_begin, fr.n_cams,
+                expo = neg_log_v<KV>(cams, C.raytab, cm.frame_cam, mine.p, fr.cam_begin, fr.n_cams,
                                      in_all, partial, P);
             }
             uint32_t rgb3 = 0;
