@@ -384,22 +384,43 @@ __device__ __forceinline__ void load_tile(const DevCam& cm, uint32_t tile, TileD
     }
 }
 
-// the pixels of a loaded tile in order: f(g, j, x, y, depth, confidence, in image, index)
+// the pixels of a loaded tile in order: f(g, j, x, y, depth, confidence, in image, index,
+// column ray, row ray), the rays from the camera's ray table `rays` (W column rays, then H
+// row rays).  When W and the table's offset are multiples of 4, a thread's 4 pixels share
+// a row and their column rays are one 16-byte load.
 template <typename F>
 __device__ __forceinline__ void visit_tile(const DevCam& cm, uint32_t tile, const TileData& t,
-                                           F&& f) {
+                                           const float* rays, F&& f) {
     const uint32_t npx = (uint32_t)cm.W * (uint32_t)cm.H;
     const uint32_t base = (tile - cm.tile_off) * (uint32_t)kPxTile;
     const uint32_t W = (uint32_t)cm.W;
+    const bool quad_rays = ((W | cm.tab_off) & 3u) == 0u;
     constexpr int NG = kPxPerThread / 4;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const uint32_t idx = base + (uint32_t)g * (kBlock * 4) + threadIdx.x * 4u;
         uint32_t y = idx / W;
         uint32_t x = idx - y * W;
+        float rxv[4], ryv[4];
+        if (quad_rays && idx < npx) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 r = *glob(reinterpret_cast<const f4*>(rays + x));
+            rxv[0] = r.x; rxv[1] = r.y; rxv[2] = r.z; rxv[3] = r.w;
+            const float ry = glob(rays)[W + y];
+            ryv[0] = ryv[1] = ryv[2] = ryv[3] = ry;
+        } else {
+            uint32_t xx = x, yy = y;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in = idx + j < npx;
+                rxv[j] = in ? glob(rays)[xx] : 0.0f;
+                ryv[j] = in ? glob(rays)[W + yy] : 0.0f;
+                if (++xx == W) { xx = 0; ++yy; }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            f(g, j, x, y, t.d[g][j], t.c[g][j], idx + j < npx, idx + j);
+            f(g, j, x, y, t.d[g][j], t.c[g][j], idx + j < npx, idx + j, rxv[j], ryv[j]);
             if (++x == W) { x = 0; ++y; }
         }
     }
@@ -408,10 +429,11 @@ __device__ __forceinline__ void visit_tile(const DevCam& cm, uint32_t tile, cons
 // every load of the thread first, then the pixels in order: the work on one group does
 // not wait for the next group's loads
 template <typename F>
-__device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile, F&& f) {
+__device__ __forceinline__ void for_tile_pixels(const DevCam& cm, uint32_t tile, const float* rays,
+                                                F&& f) {
     TileData t;
     load_tile(cm, tile, t);
-    visit_tile(cm, tile, t, f);
+    visit_tile(cm, tile, t, rays, f);
 }
 
 // ---------------------------------------------------------------- Eq. 3 confidence
@@ -591,14 +613,13 @@ __device__ __forceinline__ void ph_backproject(const Ctx& C, uint32_t tile, char
         for (uint64_t i = b0 + tid; i < b1; i += kBlock) C.counts[i] = 0;
     }
     const DevCam& cm = C.cams[cam_of_tile(C, tile)];
-    const float* rx = C.raytab + cm.tab_off;
-    const float* ry = rx + cm.W;
+    const float* rx = C.raytab + cm.tab_off;          // the camera's ray table
     const bool no_mf = P.flags & 1u;
     uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u}, cnt = 0;
-    for_tile_pixels(cm, tile, [&](int, int, uint32_t x, uint32_t y, float d, float c, bool in,
-                                  uint32_t) {
+    for_tile_pixels(cm, tile, rx, [&](int, int, uint32_t, uint32_t, float d, float c, bool in,
+                                      uint32_t, float rxj, float ryj) {
         if (!in || !gate_px(d, c, P.tau, no_mf)) return;
-        const Pt p = backproject_ray(cm, rx[x], ry[y], d);
+        const Pt p = backproject_ray(cm, rxj, ryj, d);
         if (!finite3(p)) return;
         const uint32_t o[3] = {f2o(p.x), f2o(p.y), f2o(p.z)};
 #pragma unroll
@@ -725,8 +746,7 @@ __device__ __forceinline__ void hist_tile(const Ctx& C, const DevCam& cm, uint32
                                           const TileData& td, uint32_t* s_key, uint32_t* s_cnt,
                                           uint32_t* counts, bool no_mf) {
     const DevParams& P = C.hdr->prm;
-    const float* rx = C.raytab + cm.tab_off;
-    const float* ry = rx + cm.W;
+    const float* rx = C.raytab + cm.tab_off;          // the camera's ray table
     FrameGrid g;
     frame_grid(C.fs[cm.frame], P, g);
     // add n points of cell `key` to the tile's LDS hash (global atomic if the hash is full)
@@ -761,12 +781,12 @@ __device__ __forceinline__ void hist_tile(const Ctx& C, const DevCam& cm, uint32
     };
     uint32_t kk[4];
     bool hv[4];
-    visit_tile(cm, tile, td, [&](int, int j, uint32_t x, uint32_t y, float d, float c, bool in,
-                                 uint32_t) {
+    visit_tile(cm, tile, td, rx, [&](int, int j, uint32_t, uint32_t, float d, float c, bool in,
+                                     uint32_t, float rxj, float ryj) {
         bool has = in && gate_px(d, c, P.tau, no_mf);
         uint32_t key = 0;
         if (has) {
-            const Pt p = backproject_ray(cm, rx[x], ry[y], d);
+            const Pt p = backproject_ray(cm, rxj, ryj, d);
             has = finite3(p);
             if (has) key = coarse_cell(g, p).lin;
         }
@@ -1088,8 +1108,7 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
     const uint64_t* fbase = C.fine_base + (uint64_t)cm.frame * G3;
     const bool key64 = bs->key64;
     uint32_t* s_w = reinterpret_cast<uint32_t*>(smem);
-    const float* rx = C.raytab + cm.tab_off;
-    const float* ry = rx + cm.W;
+    const float* rx = C.raytab + cm.tab_off;          // the camera's ray table
     FrameGrid g;
     if (!no_sa) frame_grid(C.fs[cm.frame], P, g);
 
@@ -1110,12 +1129,12 @@ __device__ __forceinline__ void ph_keys(const Ctx& C, uint32_t tile, char* smem)
 
     uint64_t kv[kPxPerThread];
     uint32_t mask = 0;
-    for_tile_pixels(cm, tile, [&](int gi, int j, uint32_t x, uint32_t y, float d, float c,
-                                  bool in, uint32_t) {
+    for_tile_pixels(cm, tile, rx, [&](int gi, int j, uint32_t, uint32_t, float d, float c,
+                                      bool in, uint32_t, float rxj, float ryj) {
         const int k = gi * 4 + j;
         kv[k] = 0;
         if (!in || !gate_px(d, c, P.tau, no_mf)) return;
-        const Pt p = backproject_ray(cm, rx[x], ry[y], d);
+        const Pt p = backproject_ray(cm, rxj, ryj, d);
         if (!finite3(p)) return;
         mask |= 1u << k;
         if (no_sa) return;
