@@ -79,10 +79,10 @@ def kernel_bytes(name, P, M, S, R, K, kb):
 # launches of that many frames; otherwise the traffic is reported as null.
 COUNTERS = {
     "kernel": "cells_top3_consistency_fuse",
-    "source_digest": "9fed2305b2d8d51f",
+    "source_digest": "c42fb2f44b61f40e",
     "frames_per_launch": 2,
-    "fetch_kib_per_launch": 203484.6,
-    "write_kib_per_launch": 106583.4,
+    "fetch_kib_per_launch": 203482.3,
+    "write_kib_per_launch": 106585.9,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
     # SQ_INSTS_VALU of the same launches (rocprofv3 --pmc): VALU wave-instructions issued
