@@ -54,7 +54,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(Ctx C, uint32_t pass) {
 }
 
 // The per-cell phase, with a candidate list of KV views (3 covers the common K <= 4 and
-// keeps four waves resident per SIMD; 7 covers K <= 8).
+// keeps at least four waves resident per SIMD, five at its register and LDS use; 7 covers
+// K <= 8).
 template <int KV, bool LDS_CAMS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KV <= 3 ? 4 : 3)))
 void k_cells(Ctx C) {
